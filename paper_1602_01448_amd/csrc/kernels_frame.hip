@@ -1,0 +1,679 @@
+// Frame kernels: gather (Q), 2-D FFT (F), Fourier-modulus projection (P_a),
+// inverse FFT (F*) and the RAAR / gradient epilogues, fused per frame.
+//
+// Paper references: frames z_i = w T_i psi (Sec. "Forward model", Eq.
+// (overlap)); F (Sec. "Forward model"); P_a z = F*(Fz/|Fz|) a (Eq. (Pa));
+// RAAR update (algorithm box, step 5, relaxed-averaged-alternating-
+// reflections sign); eps_a (Eq. (amplitudemetric)); probe update (Eq.
+// (standardprobe)).
+//
+// Two execution shapes:
+//  * m <= 128: one workgroup owns a group of G whole frames in LDS (G m^2 =
+//    16 NT) and runs gather -> F -> modulus -> F* -> epilogue without leaving
+//    the CU.  HBM traffic per frame pixel: carry in 8 B, a 4 B, carry out 8 B,
+//    merge input out 8 B.
+//  * m = 256: a frame (512 KiB) exceeds LDS, so the transform is split into
+//    a row pass (gather + row FFTs), a column pass (column FFTs + modulus +
+//    inverse column FFTs) and a row pass (inverse row FFTs + epilogue), with
+//    the row-transformed frames kept in an HBM stage buffer between passes.
+#include "fft_lds.hpp"
+#include "sharp_internal.hpp"
+
+namespace sharp {
+
+// ---------------------------------------------------------------------------
+// LDS layouts for fft_stage
+// ---------------------------------------------------------------------------
+template <int M>
+struct RowLay {  // consecutive lines of length M (rows of the frames held)
+    static constexpr int stride = 1;
+    template <int BPL> __device__ static int base(int b) { return (b / BPL) * M; }
+    template <int BPL> __device__ static int j(int b) { return b % BPL; }
+};
+
+template <int M>
+struct ColLayFG {  // columns of G whole frames stored [f][y][x]; x fastest over lanes
+    static constexpr int stride = M;
+    template <int BPL> __device__ static int base(int b) { return ((b / M) / BPL) * M * M + b % M; }
+    template <int BPL> __device__ static int j(int b) { return (b / M) % BPL; }
+};
+
+template <int CB>
+struct ColLayCB {  // CB columns of one frame stored [y][c]
+    static constexpr int stride = CB;
+    template <int BPL> __device__ static int base(int b) { return b % CB; }
+    template <int BPL> __device__ static int j(int b) { return b / CB; }
+};
+
+// fft_stage needs Lay::base/j as plain templates; adapt the member templates.
+template <class Lay, int BPL> struct LayAt {
+    static constexpr int stride = Lay::stride;
+    __device__ static int base(int b) { return Lay::template base<BPL>(b); }
+    __device__ static int j(int b) { return Lay::template j<BPL>(b); }
+};
+
+template <int N, int DIR, int NT, int NLINES, class Lay, class Post>
+__device__ __forceinline__ void fft_1d(float2* lds, const float2* twl, Post& post) {
+    using P = Radix<N>;
+    NoPost none;
+    if constexpr (P::S == 1) {
+        fft_stage<N, P::R0, 1, DIR, NT, NLINES * (N / P::R0), LayAt<Lay, N / P::R0>>(lds, twl, post);
+    } else {
+        fft_stage<N, P::R0, 1, DIR, NT, NLINES * (N / P::R0), LayAt<Lay, N / P::R0>>(lds, twl, none);
+        fft_stage<N, P::R1, P::R0, DIR, NT, NLINES * (N / P::R1), LayAt<Lay, N / P::R1>>(lds, twl, post);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// shared pieces
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap(int v, int n) { return v >= n ? v - n : v; }
+
+__device__ __forceinline__ float2 ldc(const float2* p, size_t i) { return p[i]; }
+
+__device__ __forceinline__ void ld2(const float2* __restrict__ p, size_t i, float2& a, float2& b) {
+    float4 t = *reinterpret_cast<const float4*>(p + i);
+    a = make_float2(t.x, t.y);
+    b = make_float2(t.z, t.w);
+}
+__device__ __forceinline__ void st2(float2* __restrict__ p, size_t i, float2 a, float2 b) {
+    *reinterpret_cast<float4*>(p + i) = make_float4(a.x, a.y, b.x, b.y);
+}
+
+// Gather of two horizontally adjacent object pixels for frame pixel (y, x), (y, x+1).
+__device__ __forceinline__ void gather2(const FrameArgs& A, int frame, int y, int x, float2& p0, float2& p1) {
+    const int py = A.pos[2 * frame], px = A.pos[2 * frame + 1];
+    int gy = py + y, gx = px + x, gx1 = gx + 1;
+    if (A.periodic) {
+        gy = wrap(gy, A.ny);
+        gx = wrap(gx, A.nx);
+        gx1 = wrap(gx1, A.nx);
+    }
+    const float2* row = A.psi + (size_t)gy * A.nx;
+    p0 = row[gx];
+    p1 = row[gx1];
+}
+
+// Prologue: the frame values z entering the transform (and T psi for GRAD).
+template <int MODE>
+__device__ __forceinline__ void prologue2(const FrameArgs& A, int frame, int y, int x, size_t gidx, int pix,
+                                          float2& z0, float2& z1, float2& t0, float2& t1) {
+    if constexpr (MODE == FM_RAAR) {
+        float2 p0, p1, w0, w1;
+        ld2(A.u, gidx, z0, z1);
+        gather2(A, frame, y, x, p0, p1);
+        ld2(A.w_g, pix, w0, w1);
+        z0 = cadd(z0, cscale(cmul(w0, p0), A.g));
+        z1 = cadd(z1, cscale(cmul(w1, p1), A.g));
+    } else if constexpr (MODE == FM_PA || MODE == FM_F || MODE == FM_FINV) {
+        ld2(A.in, gidx, z0, z1);
+    } else {  // GRAD, SIM, Q
+        float2 w0, w1;
+        gather2(A, frame, y, x, t0, t1);
+        ld2(A.w, pix, w0, w1);
+        z0 = cmul(w0, t0);
+        z1 = cmul(w1, t1);
+    }
+}
+
+// Fourier-domain operation applied to the last forward stage's outputs.
+// `addr_to_g` maps the LDS element address to (frame, global index).
+template <int MODE, int M>
+struct ModOp {
+    const float* __restrict__ a;
+    float* __restrict__ out_f;
+    float resid = 0.f;
+    __device__ __forceinline__ void apply(bool ok, size_t gi, float2& v) {
+        v = cscale(v, 1.0f / M);  // unitary scaling of F
+        if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
+            const float av = ok ? a[gi] : 0.f;
+            const float n2 = cabs2(v);
+            const float mag = sqrtf(n2);
+            float2 s = make_float2(1.f, 0.f);  // sgn(0) := 1
+            if (n2 > 0.f) s = cscale(v, 1.0f / mag);
+            const float d = mag - av;
+            if (ok) resid += d * d;
+            const float2 p = cscale(s, av);
+            v = (MODE == FM_GRAD) ? csub(v, p) : p;
+        } else if constexpr (MODE == FM_SIM) {
+            if (ok) out_f[gi] = cabs2(v);
+        }
+    }
+};
+
+__device__ __forceinline__ float block_sum(float x, float* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = x;
+    __syncthreads();
+    float s = 0.f;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += red[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// m <= 128: whole frames in LDS
+// ---------------------------------------------------------------------------
+template <int M>
+struct FG {
+    static constexpr int NT = (M == 128) ? 1024 : 256;
+    static constexpr int E = 16;
+    static constexpr int G = NT * E / (M * M);
+    static constexpr int FE = G * M * M;
+    static constexpr int NP = E / 2;
+    static constexpr int LDS = pidx(FE);
+    static constexpr size_t SMEM = (size_t)(LDS + M) * sizeof(float2);
+};
+
+template <int M, int MODE>
+struct FGPost {
+    ModOp<MODE, M> op;
+    int frame0, K;
+    __device__ __forceinline__ void operator()(int addr, float2& v) {
+        const int frame = frame0 + addr / (M * M);
+        const bool ok = frame < K;
+        op.apply(ok, (size_t)frame * M * M + addr % (M * M), v);
+    }
+};
+
+// fft_stage calls post(b, e, v); wrap to give the LDS element address instead.
+template <class Lay, class P>
+struct AddrPost {
+    P* p;
+    __device__ __forceinline__ void operator()(int b, int e, float2& v) const {
+        (*p)(Lay::base(b) + e * Lay::stride, v);
+    }
+};
+
+template <int N, int DIR, int NT, int NLINES, class Lay, class P>
+__device__ __forceinline__ void fft_1d_post(float2* lds, const float2* twl, P& post) {
+    using PR = Radix<N>;
+    NoPost none;
+    if constexpr (PR::S == 1) {
+        using L0 = LayAt<Lay, N / PR::R0>;
+        AddrPost<L0, P> ap{&post};
+        fft_stage<N, PR::R0, 1, DIR, NT, NLINES * (N / PR::R0), L0>(lds, twl, ap);
+    } else {
+        using L0 = LayAt<Lay, N / PR::R0>;
+        using L1 = LayAt<Lay, N / PR::R1>;
+        AddrPost<L1, P> ap{&post};
+        fft_stage<N, PR::R0, 1, DIR, NT, NLINES * (N / PR::R0), L0>(lds, twl, none);
+        fft_stage<N, PR::R1, PR::R0, DIR, NT, NLINES * (N / PR::R1), L1>(lds, twl, ap);
+    }
+}
+
+template <int M, int MODE>
+__global__ void __launch_bounds__(FG<M>::NT) fg_kernel(FrameArgs A) {
+    using C = FG<M>;
+    constexpr int NT = C::NT, G = C::G, NP = C::NP, MM = M * M;
+    extern __shared__ float2 smem[];
+    __shared__ float red[NT / 64];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
+
+    float resid = 0.f;
+    float2 gacc[2 * NP];
+#pragma unroll
+    for (int i = 0; i < 2 * NP; ++i) gacc[i] = make_float2(0.f, 0.f);
+
+    const int ngroups = (A.K + G - 1) / G;
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        float2 z[2 * NP], t[2 * NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int f = e0 / MM, rem = e0 % MM, y = rem / M, x = rem % M;
+            const int frame = grp * G + f;
+            z[2 * k] = z[2 * k + 1] = t[2 * k] = t[2 * k + 1] = make_float2(0.f, 0.f);
+            if (frame < A.K)
+                prologue2<MODE>(A, frame, y, x, (size_t)frame * MM + rem, rem, z[2 * k], z[2 * k + 1],
+                                t[2 * k], t[2 * k + 1]);
+            if constexpr (MODE == FM_Q) {
+                if (frame < A.K) st2(A.out, (size_t)frame * MM + rem, z[2 * k], z[2 * k + 1]);
+            } else {
+                lds[pidx(e0)] = z[2 * k];
+                lds[pidx(e0 + 1)] = z[2 * k + 1];
+            }
+        }
+        if constexpr (MODE == FM_Q) continue;
+        __syncthreads();
+
+        constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
+        NoPost none;
+        fft_1d<M, D1, NT, G * M, RowLay<M>>(lds, twl, none);
+        FGPost<M, MODE> post{{A.a, A.out_f, 0.f}, grp * G, A.K};
+        fft_1d_post<M, D1, NT, G * M, ColLayFG<M>>(lds, twl, post);
+        resid += post.op.resid;
+        if constexpr (MODE == FM_SIM) continue;
+        if constexpr (MODE == FM_F || MODE == FM_FINV) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const int e0 = 2 * (threadIdx.x + NT * k);
+                const int f = e0 / MM, rem = e0 % MM, frame = grp * G + f;
+                if (frame < A.K) st2(A.out, (size_t)frame * MM + rem, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+            }
+            __syncthreads();
+            continue;
+        }
+        fft_1d<M, -1, NT, G * M, RowLay<M>>(lds, twl, none);
+        fft_1d<M, -1, NT, G * M, ColLayFG<M>>(lds, twl, none);
+        const float inv_m = 1.0f / M;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int f = e0 / MM, rem = e0 % MM, frame = grp * G + f;
+            if (frame >= A.K) continue;
+            const size_t gi = (size_t)frame * MM + rem;
+            const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
+            if constexpr (MODE == FM_RAAR) {
+                float2 w0, w1;
+                ld2(A.w, rem, w0, w1);
+                const float b = A.beta, c = 1.f - 2.f * A.beta;
+                st2(A.u, gi, cadd(cscale(z[2 * k], b), cscale(y0, c)), cadd(cscale(z[2 * k + 1], b), cscale(y1, c)));
+                st2(A.v, gi, cconjmul(w0, csub(cscale(y0, 2.f), z[2 * k])),
+                    cconjmul(w1, csub(cscale(y1, 2.f), z[2 * k + 1])));
+            } else if constexpr (MODE == FM_PA) {
+                st2(A.out, gi, y0, y1);
+            } else if constexpr (MODE == FM_GRAD) {
+                float2 w0, w1;
+                ld2(A.w, rem, w0, w1);
+                const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
+                st2(A.v, gi, cconjmul(w0, r0), cconjmul(w1, r1));
+                gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t[2 * k], r0));
+                gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t[2 * k + 1], r1));
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
+        const float s = block_sum(resid, red);
+        if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
+    }
+    if constexpr (MODE == FM_GRAD) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int f = e0 / MM, rem = e0 % MM;
+            st2(A.gw_part, ((size_t)blockIdx.x * G + f) * MM + rem, gacc[2 * k], gacc[2 * k + 1]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// m = 256: three passes through an HBM stage buffer
+// ---------------------------------------------------------------------------
+template <int M>
+struct MP {
+    static constexpr int NT = 256, E = 16, NP = E / 2;
+    static constexpr int RB = NT * E / M;  // rows per row-pass workgroup
+    static constexpr int CB = NT * E / M;  // columns per column-pass workgroup
+    static constexpr int LDS = pidx(NT * E);
+    static constexpr size_t SMEM = (size_t)(LDS + M) * sizeof(float2);
+};
+
+// Row pass forward: prologue + row FFTs -> stage
+template <int M, int MODE>
+__global__ void __launch_bounds__(256) mp_row_fwd(FrameArgs A) {
+    using C = MP<M>;
+    constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = M / RB;
+    extern __shared__ float2 smem[];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
+    const int items = A.K * NRB;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int frame = it / NRB, rb = it % NRB;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int y = rb * RB + e0 / M, x = e0 % M, rem = y * M + x;
+            float2 z0, z1, t0, t1;
+            prologue2<MODE>(A, frame, y, x, (size_t)frame * MM + rem, rem, z0, z1, t0, t1);
+            lds[pidx(e0)] = z0;
+            lds[pidx(e0 + 1)] = z1;
+        }
+        __syncthreads();
+        constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
+        NoPost none;
+        fft_1d<M, D1, NT, RB, RowLay<M>>(lds, twl, none);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int y = rb * RB + e0 / M, x = e0 % M;
+            st2(A.stage, (size_t)frame * MM + y * M + x, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+        }
+        __syncthreads();
+    }
+}
+
+template <int M, int MODE>
+struct CBPost {
+    ModOp<MODE, M> op;
+    size_t fbase;
+    int x0;
+    __device__ __forceinline__ void operator()(int addr, float2& v) {
+        constexpr int CB = MP<M>::CB;
+        op.apply(true, fbase + (size_t)(addr / CB) * M + x0 + addr % CB, v);
+    }
+};
+
+// Column pass: column FFTs + Fourier op (+ inverse column FFTs)
+template <int M, int MODE>
+__global__ void __launch_bounds__(256) mp_col(FrameArgs A) {
+    using C = MP<M>;
+    constexpr int NT = C::NT, NP = C::NP, CB = C::CB, MM = M * M, NCB = M / CB;
+    extern __shared__ float2 smem[];
+    __shared__ float red[NT / 64];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
+    float resid = 0.f;
+    const int items = A.K * NCB;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int frame = it / NCB, cb = it % NCB;
+        const size_t fb = (size_t)frame * MM;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int y = e0 / CB, c = e0 % CB;
+            float2 a0, a1;
+            ld2(A.stage, fb + (size_t)y * M + cb * CB + c, a0, a1);
+            lds[pidx(e0)] = a0;
+            lds[pidx(e0 + 1)] = a1;
+        }
+        __syncthreads();
+        constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
+        CBPost<M, MODE> post{{A.a, A.out_f, 0.f}, fb, cb * CB};
+        fft_1d_post<M, D1, NT, CB, ColLayCB<CB>>(lds, twl, post);
+        resid += post.op.resid;
+        if constexpr (MODE == FM_SIM) continue;
+        float2* dst = A.stage;
+        if constexpr (MODE == FM_F || MODE == FM_FINV) {
+            dst = A.out;
+        } else {
+            NoPost none;
+            fft_1d<M, -1, NT, CB, ColLayCB<CB>>(lds, twl, none);
+        }
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int y = e0 / CB, c = e0 % CB;
+            st2(dst, fb + (size_t)y * M + cb * CB + c, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
+        const float s = block_sum(resid, red);
+        if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
+    }
+}
+
+// Row pass inverse: inverse row FFTs + epilogue
+template <int M, int MODE>
+__global__ void __launch_bounds__(256) mp_row_inv(FrameArgs A) {
+    using C = MP<M>;
+    constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = M / RB;
+    extern __shared__ float2 smem[];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
+    float2 gacc[2 * NP];
+#pragma unroll
+    for (int i = 0; i < 2 * NP; ++i) gacc[i] = make_float2(0.f, 0.f);
+    const int items = A.K * NRB;
+    int rb_fixed = blockIdx.x % NRB;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int frame = it / NRB, rb = it % NRB;
+        const size_t fb = (size_t)frame * MM;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int y = rb * RB + e0 / M, x = e0 % M;
+            float2 a0, a1;
+            ld2(A.stage, fb + (size_t)y * M + x, a0, a1);
+            lds[pidx(e0)] = a0;
+            lds[pidx(e0 + 1)] = a1;
+        }
+        __syncthreads();
+        NoPost none;
+        fft_1d<M, -1, NT, RB, RowLay<M>>(lds, twl, none);
+        const float inv_m = 1.0f / M;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int y = rb * RB + e0 / M, x = e0 % M, rem = y * M + x;
+            const size_t gi = fb + rem;
+            const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
+            if constexpr (MODE == FM_RAAR) {
+                float2 z0, z1, t0, t1, w0, w1;
+                prologue2<MODE>(A, frame, y, x, gi, rem, z0, z1, t0, t1);
+                ld2(A.w, rem, w0, w1);
+                const float b = A.beta, c = 1.f - 2.f * A.beta;
+                st2(A.u, gi, cadd(cscale(z0, b), cscale(y0, c)), cadd(cscale(z1, b), cscale(y1, c)));
+                st2(A.v, gi, cconjmul(w0, csub(cscale(y0, 2.f), z0)), cconjmul(w1, csub(cscale(y1, 2.f), z1)));
+            } else if constexpr (MODE == FM_PA) {
+                st2(A.out, gi, y0, y1);
+            } else if constexpr (MODE == FM_GRAD) {
+                float2 t0, t1, w0, w1;
+                gather2(A, frame, y, x, t0, t1);
+                ld2(A.w, rem, w0, w1);
+                const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
+                st2(A.v, gi, cconjmul(w0, r0), cconjmul(w1, r1));
+                gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t0, r0));
+                gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t1, r1));
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == FM_GRAD) {
+        // gridDim.x is a multiple of NRB, so this block only saw row block rb_fixed.
+        const int slot = blockIdx.x / NRB;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int y = rb_fixed * RB + e0 / M, x = e0 % M;
+            st2(A.gw_part, (size_t)slot * MM + y * M + x, gacc[2 * k], gacc[2 * k + 1]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Q alone for any m (no transform): out = w T psi
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(256) q_kernel(FrameArgs A) {
+    constexpr int MM = M * M;
+    const size_t npairs = (size_t)A.K * MM / 2;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < npairs; i += (size_t)gridDim.x * 256) {
+        const size_t e0 = 2 * i;
+        const int frame = (int)(e0 / MM), rem = (int)(e0 % MM), y = rem / M, x = rem % M;
+        float2 z0, z1, t0, t1;
+        prologue2<FM_Q>(A, frame, y, x, e0, rem, z0, z1, t0, t1);
+        st2(A.out, e0, z0, z1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int M, int MODE>
+static hipError_t launch_fg(const FrameArgs& A, int grid, hipStream_t s) {
+    using C = FG<M>;
+    auto k = fg_kernel<M, MODE>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), C::SMEM, s, A);
+    return hipGetLastError();
+}
+
+template <int M, int MODE>
+static hipError_t launch_mp(const FrameArgs& A, int grid_rows, int grid_cols, int grid_inv, hipStream_t s) {
+    using C = MP<M>;
+    hipLaunchKernelGGL((mp_row_fwd<M, MODE>), dim3(grid_rows), dim3(C::NT), C::SMEM, s, A);
+    hipLaunchKernelGGL((mp_col<M, MODE>), dim3(grid_cols), dim3(C::NT), C::SMEM, s, A);
+    if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD)
+        hipLaunchKernelGGL((mp_row_inv<M, MODE>), dim3(grid_inv), dim3(C::NT), C::SMEM, s, A);
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t dispatch_m(int mode, const FrameArgs& A, int grid_hint, hipStream_t s, int* blocks_used) {
+    if (mode == FM_Q) {
+        const size_t npairs = (size_t)A.K * M * M / 2;
+        int grid = (int)std::min<size_t>((npairs + 255) / 256, 65536);
+        hipLaunchKernelGGL(q_kernel<M>, dim3(grid), dim3(256), 0, s, A);
+        if (blocks_used) *blocks_used = 0;
+        return hipGetLastError();
+    }
+    if constexpr (M <= 128) {
+        using C = FG<M>;
+        const int ngroups = (A.K + C::G - 1) / C::G;
+        int grid = ngroups;
+        if (mode == FM_GRAD && grid_hint > 0) grid = std::min(ngroups, grid_hint);
+        if (blocks_used) *blocks_used = grid;
+        switch (mode) {
+            case FM_RAAR: return launch_fg<M, FM_RAAR>(A, grid, s);
+            case FM_PA: return launch_fg<M, FM_PA>(A, grid, s);
+            case FM_GRAD: return launch_fg<M, FM_GRAD>(A, grid, s);
+            case FM_SIM: return launch_fg<M, FM_SIM>(A, grid, s);
+            case FM_F: return launch_fg<M, FM_F>(A, grid, s);
+            case FM_FINV: return launch_fg<M, FM_FINV>(A, grid, s);
+        }
+        return hipErrorInvalidValue;
+    } else {
+        using C = MP<M>;
+        const int items = A.K * (M / C::RB);
+        int ginv = items;
+        if (mode == FM_GRAD && grid_hint > 0) {
+            const int nrb = M / C::RB;
+            ginv = std::max(nrb, std::min(items, (grid_hint / nrb) * nrb));
+        }
+        if (blocks_used) *blocks_used = (mode == FM_GRAD) ? ginv : items;
+        switch (mode) {
+            case FM_RAAR: return launch_mp<M, FM_RAAR>(A, items, items, ginv, s);
+            case FM_PA: return launch_mp<M, FM_PA>(A, items, items, ginv, s);
+            case FM_GRAD: return launch_mp<M, FM_GRAD>(A, items, items, ginv, s);
+            case FM_SIM: return launch_mp<M, FM_SIM>(A, items, items, ginv, s);
+            case FM_F: return launch_mp<M, FM_F>(A, items, items, ginv, s);
+            case FM_FINV: return launch_mp<M, FM_FINV>(A, items, items, ginv, s);
+        }
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_frame(int mode, const FrameArgs& A, int grid_hint, hipStream_t s, int* blocks_used) {
+    switch (A.M) {
+        case 16: return dispatch_m<16>(mode, A, grid_hint, s, blocks_used);
+        case 32: return dispatch_m<32>(mode, A, grid_hint, s, blocks_used);
+        case 64: return dispatch_m<64>(mode, A, grid_hint, s, blocks_used);
+        case 128: return dispatch_m<128>(mode, A, grid_hint, s, blocks_used);
+        case 256: return dispatch_m<256>(mode, A, grid_hint, s, blocks_used);
+    }
+    return hipErrorInvalidValue;
+}
+
+int frame_partial_slots(int M, int mode, int blocks) {
+    if (mode != FM_GRAD) return 0;
+    switch (M) {
+        case 16: return blocks * FG<16>::G;
+        case 32: return blocks * FG<32>::G;
+        case 64: return blocks * FG<64>::G;
+        case 128: return blocks * FG<128>::G;
+        case 256: return blocks / (256 / MP<256>::RB);
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// probe update (Eq. (standardprobe)): per frame-chunk partial sums of
+// conj(T psi_l) z and |T psi_l|^2 with z = u' + beta w T psi_v, then w = num/den
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) probe_partial_kernel(int M, int K, const int* __restrict__ pos, int nx,
+                                                            int ny, int periodic, const float2* __restrict__ u,
+                                                            const float2* __restrict__ w,
+                                                            const float2* __restrict__ psi_v,
+                                                            const float2* __restrict__ psi_l, float beta,
+                                                            int chunks, float2* __restrict__ num,
+                                                            float* __restrict__ den) {
+    const int MM = M * M;
+    const int p = blockIdx.y * 256 + threadIdx.x;  // pixel index in the frame
+    if (p >= MM) return;
+    const int c = blockIdx.x;
+    const int f0 = (int)((long long)K * c / chunks), f1 = (int)((long long)K * (c + 1) / chunks);
+    const int y = p / M, x = p % M;
+    const float2 wp = w[p];
+    float2 acc = make_float2(0.f, 0.f);
+    float d = 0.f;
+    for (int f = f0; f < f1; ++f) {
+        int gy = pos[2 * f] + y, gx = pos[2 * f + 1] + x;
+        if (periodic) {
+            gy = wrap(gy, ny);
+            gx = wrap(gx, nx);
+        }
+        const size_t o = (size_t)gy * nx + gx;
+        const float2 zf = cadd(u[(size_t)f * MM + p], cscale(cmul(wp, psi_v[o]), beta));
+        const float2 t = psi_l[o];
+        acc = cadd(acc, cconjmul(t, zf));
+        d += cabs2(t);
+    }
+    num[(size_t)c * MM + p] = acc;
+    den[(size_t)c * MM + p] = d;
+}
+
+__global__ void __launch_bounds__(256) probe_finish_kernel(int MM, int chunks, const float2* __restrict__ num,
+                                                           const float* __restrict__ den, float2* __restrict__ w_gat,
+                                                           float2* __restrict__ w_cur) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= MM) return;
+    float2 n = make_float2(0.f, 0.f);
+    float d = 0.f;
+    for (int c = 0; c < chunks; ++c) {
+        n = cadd(n, num[(size_t)c * MM + p]);
+        d += den[(size_t)c * MM + p];
+    }
+    const float2 old = w_cur[p];
+    w_gat[p] = old;
+    w_cur[p] = d > 0.f ? cscale(n, 1.0f / d) : make_float2(0.f, 0.f);
+}
+
+__global__ void __launch_bounds__(256) gw_finish_kernel(int MM, int slots, const float2* __restrict__ part,
+                                                        float2* __restrict__ gw) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= MM) return;
+    float2 s = make_float2(0.f, 0.f);
+    for (int c = 0; c < slots; ++c) s = cadd(s, part[(size_t)c * MM + p]);
+    gw[p] = s;
+}
+
+hipError_t launch_probe_partial(int M, int K, const int* pos, int nx, int ny, int periodic, const float2* u,
+                                const float2* w, const float2* psi_v, const float2* psi_l, float beta, int chunks,
+                                float2* num, float* den, hipStream_t s) {
+    dim3 grid(chunks, (M * M + 255) / 256);
+    hipLaunchKernelGGL(probe_partial_kernel, grid, dim3(256), 0, s, M, K, pos, nx, ny, periodic, u, w, psi_v, psi_l,
+                       beta, chunks, num, den);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_finish(int M, int chunks, const float2* num, const float* den, float2* w_gat, float2* w_cur,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(probe_finish_kernel, dim3((M * M + 255) / 256), dim3(256), 0, s, M * M, chunks, num, den,
+                       w_gat, w_cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_gw_finish(int M, int slots, const float2* part, float2* gw, hipStream_t s) {
+    hipLaunchKernelGGL(gw_finish_kernel, dim3((M * M + 255) / 256), dim3(256), 0, s, M * M, slots, part, gw);
+    return hipGetLastError();
+}
+
+}  // namespace sharp

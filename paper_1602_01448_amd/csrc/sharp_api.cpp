@@ -1,0 +1,672 @@
+// Host side of the C ABI declared in include/sharp.h: argument validation,
+// the tile -> frame incidence lists of the overlap merge (the per-block
+// contributing-frame lists of Sec. "Computational Methodology"), workspace
+// layout, and the launch sequences of one RAAR iteration (algorithm box,
+// steps 5-7).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/sharp.h"
+#include "sharp_internal.hpp"
+
+using namespace sharp;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool supported_m(int m) { return m == 16 || m == 32 || m == 64 || m == 128 || m == 256; }
+
+// frames per frame-kernel group (must match kernels_frame.hip)
+int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
+
+struct Offsets {
+    size_t tw, pos, tile_ptr, tile_frames, a, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
+    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, total;
+};
+
+}  // namespace
+
+struct sharp_plan_s {
+    int nx = 0, ny = 0, m = 0, K = 0;
+    sharp_options opt{};
+    std::vector<int32_t> pos;
+    int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
+    std::vector<int32_t> tile_ptr, tile_frames;
+    Offsets off{};
+    size_t resid_cap = 0, gw_slots = 0;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool has_ws = false, has_data = false, has_probe = false, has_object = false;
+    float g = 1.f;
+    long long iter = 0, hist_count = 0;
+    bool gat_stale = false, last_probe_updated = false;
+
+    template <class T> T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+    size_t frame_elems() const { return (size_t)K * m * m; }
+    size_t obj_elems() const { return (size_t)nx * ny; }
+};
+
+struct sharp_batch_s;  // defined in sharp_batch.cpp
+
+extern "C" const char* sharp_status_string(int s) {
+    switch (s) {
+        case SHARP_OK: return "ok";
+        case SHARP_ERR_INVALID_ARG: return "invalid argument";
+        case SHARP_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+        case SHARP_ERR_POSITION_OUT_OF_RANGE: return "frame position out of range";
+        case SHARP_ERR_NOT_READY: return "not ready (workspace, data, probe or object missing)";
+        case SHARP_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case SHARP_ERR_NONFINITE: return "non-finite value in data or iterate";
+        case SHARP_ERR_HIP: return "HIP runtime error";
+        case SHARP_ERR_HOST_ALLOC: return "host allocation failed";
+    }
+    return "unknown status";
+}
+
+// ---------------------------------------------------------------------------
+// plan creation
+// ---------------------------------------------------------------------------
+static void build_csr(sharp_plan_s& p) {
+    const int T = p.T, m = p.m;
+    p.tiles_x = (p.nx + T - 1) / T;
+    p.tiles_y = (p.ny + T - 1) / T;
+    p.ntiles = p.tiles_x * p.tiles_y;
+    // tile rows / columns touched by a frame (two wrapped segments at most)
+    auto spans = [&](int start, int n, int ntl, std::vector<int>& out) {
+        out.clear();
+        for (int r = 0; r < m; ++r) {
+            int v = start + r;
+            if (v >= n) v -= n;  // periodic only; non-periodic never exceeds n-1
+            const int t = v / T;
+            if (out.empty() || out.back() != t) {
+                if (std::find(out.begin(), out.end(), t) == out.end()) out.push_back(t);
+            }
+        }
+        (void)ntl;
+    };
+    std::vector<int> count(p.ntiles, 0), rows, cols;
+    for (int i = 0; i < p.K; ++i) {
+        spans(p.pos[2 * i], p.ny, p.tiles_y, rows);
+        spans(p.pos[2 * i + 1], p.nx, p.tiles_x, cols);
+        for (int ty : rows)
+            for (int tx : cols) ++count[ty * p.tiles_x + tx];
+    }
+    p.tile_ptr.assign(p.ntiles + 1, 0);
+    for (int t = 0; t < p.ntiles; ++t) p.tile_ptr[t + 1] = p.tile_ptr[t] + count[t];
+    p.tile_frames.assign(p.tile_ptr[p.ntiles], 0);
+    std::vector<int> fill(p.tile_ptr.begin(), p.tile_ptr.end() - 1);
+    for (int i = 0; i < p.K; ++i) {  // ascending frame order inside every tile
+        spans(p.pos[2 * i], p.ny, p.tiles_y, rows);
+        spans(p.pos[2 * i + 1], p.nx, p.tiles_x, cols);
+        for (int ty : rows)
+            for (int tx : cols) p.tile_frames[fill[ty * p.tiles_x + tx]++] = i;
+    }
+}
+
+static void choose_tuning(sharp_plan_s& p) {
+    // tile side: small objects use small tiles so that enough workgroups exist
+    if (p.opt.tile) p.T = p.opt.tile;
+    else p.T = (std::min(p.nx, p.ny) <= 256) ? 16 : 32;
+    build_csr(p);
+    int maxf = 0;
+    for (int t = 0; t < p.ntiles; ++t) maxf = std::max(maxf, p.tile_ptr[t + 1] - p.tile_ptr[t]);
+    if (p.opt.merge_split) p.split = p.opt.merge_split;
+    else {
+        // aim for >= 1024 workgroups in the first merge pass, >= 4 frames per chunk
+        int s = (1024 + p.ntiles - 1) / p.ntiles;
+        s = std::min(s, std::max(1, maxf / 4));
+        p.split = std::max(1, s);
+    }
+    const int groups = (p.m == 256) ? p.K * 16 : (p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
+    if (p.opt.grad_groups) p.grad_groups = p.opt.grad_groups;
+    else p.grad_groups = (p.m == 256) ? 1024 : std::min(groups, p.m == 128 ? 256 : 512);
+    if (p.m == 256) p.grad_groups = std::max(16, p.grad_groups / 16 * 16);
+    p.probe_chunks = std::min(p.K, 128);
+}
+
+static void layout(sharp_plan_s& p) {
+    Offsets& o = p.off;
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = cur;
+        cur = align_up(cur + bytes);
+        return at;
+    };
+    const size_t FE = p.frame_elems(), OE = p.obj_elems(), MM = (size_t)p.m * p.m;
+    o.tw = take(p.m * sizeof(float2));
+    o.pos = take((size_t)p.K * 2 * sizeof(int32_t));
+    o.tile_ptr = take((p.ntiles + 1) * sizeof(int32_t));
+    o.tile_frames = take(std::max<size_t>(p.tile_frames.size(), 1) * sizeof(int32_t));
+    o.a = take(FE * sizeof(float));
+    o.u = take(FE * sizeof(float2));
+    o.v = take(FE * sizeof(float2));
+    o.stage = take(p.m == 256 ? FE * sizeof(float2) : 0);
+    o.psi_v = take(OE * sizeof(float2));
+    o.psi_l = take(OE * sizeof(float2));
+    o.tmp_obj = take(OE * sizeof(float2));
+    o.D = take(OE * sizeof(float));
+    o.Dinv = take(OE * sizeof(float));
+    o.w_cur = take(MM * sizeof(float2));
+    o.w_gat = take(MM * sizeof(float2));
+    o.tmp_w = take(MM * sizeof(float2));
+    o.tmp_w2 = take(MM * sizeof(float2));
+    o.mpart = take(p.split > 1 ? (size_t)p.ntiles * p.split * p.T * p.T * 2 * sizeof(float4) : 0);
+    o.pnum = take((size_t)p.probe_chunks * MM * sizeof(float2));
+    o.pden = take((size_t)p.probe_chunks * MM * sizeof(float));
+    p.gw_slots = frame_partial_slots(p.m, FM_GRAD, p.m == 256 ? p.grad_groups : p.grad_groups);
+    o.gwpart = take(std::max<size_t>(p.gw_slots, 1) * MM * sizeof(float2));
+    const size_t groups = (p.m == 256) ? (size_t)p.K * 16 : (size_t)(p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
+    p.resid_cap = std::max<size_t>(groups, 2048);
+    o.resid = take(p.resid_cap * sizeof(float));
+    o.hist = take(kHistCap * sizeof(float));
+    o.scal = take(16 * sizeof(float));
+    o.flag = take(16 * sizeof(int));
+    o.total = cur;
+}
+
+extern "C" int sharp_plan_create(sharp_plan* out, int nx, int ny, int m, int K, const int32_t* h_pos,
+                                 const sharp_options* opt) {
+    if (!out || !h_pos) return SHARP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (K < 1 || nx < 1 || ny < 1) return SHARP_ERR_INVALID_ARG;
+    if (!supported_m(m) || m > nx || m > ny) return SHARP_ERR_UNSUPPORTED_SIZE;
+    if ((long long)K * m * m > 2147483647LL || (long long)nx * ny > 2147483647LL) return SHARP_ERR_UNSUPPORTED_SIZE;
+    sharp_options o{};
+    if (opt) {
+        o = *opt;
+        for (int r : o.reserved)
+            if (r != 0) return SHARP_ERR_INVALID_ARG;
+        if (o.periodic < 0 || o.periodic > 1 || o.probe_every < 0 || o.probe_start < 0 || !(o.eps_D >= 0.f) ||
+            !(o.tile == 0 || o.tile == 16 || o.tile == 32 || o.tile == 64) || o.merge_split < 0 ||
+            o.merge_split > 4096 || o.grad_groups < 0)
+            return SHARP_ERR_INVALID_ARG;
+    }
+    if (o.probe_start == 0) o.probe_start = 1;
+    for (int i = 0; i < K; ++i) {
+        const int y = h_pos[2 * i], x = h_pos[2 * i + 1];
+        const bool ok = o.periodic ? (y >= 0 && y < ny && x >= 0 && x < nx)
+                                   : (y >= 0 && y <= ny - m && x >= 0 && x <= nx - m);
+        if (!ok) return SHARP_ERR_POSITION_OUT_OF_RANGE;
+    }
+    sharp_plan_s* p = new (std::nothrow) sharp_plan_s();
+    if (!p) return SHARP_ERR_HOST_ALLOC;
+    try {
+        p->nx = nx;
+        p->ny = ny;
+        p->m = m;
+        p->K = K;
+        p->opt = o;
+        p->pos.assign(h_pos, h_pos + 2 * (size_t)K);
+        choose_tuning(*p);
+        layout(*p);
+    } catch (...) {
+        delete p;
+        return SHARP_ERR_HOST_ALLOC;
+    }
+    *out = p;
+    return SHARP_OK;
+}
+
+extern "C" void sharp_plan_destroy(sharp_plan p) { delete p; }
+
+extern "C" size_t sharp_workspace_bytes(sharp_plan p) { return p ? p->off.total : 0; }
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return SHARP_ERR_HIP; \
+    } while (0)
+
+extern "C" int sharp_set_stream(sharp_plan p, void* stream) {
+    if (!p) return SHARP_ERR_INVALID_ARG;
+    p->stream = (hipStream_t)stream;
+    return SHARP_OK;
+}
+
+static int density(sharp_plan_s& p);
+
+extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
+    if (!p || !d || ((uintptr_t)d % kAlign) != 0) return SHARP_ERR_INVALID_ARG;
+    if (bytes < p->off.total) return SHARP_ERR_WORKSPACE_TOO_SMALL;
+    p->ws = (char*)d;
+    p->ws_bytes = bytes;
+    p->has_ws = true;
+    p->has_data = p->has_probe = p->has_object = false;
+    std::vector<float2> tw(p->m);
+    for (int t = 0; t < p->m; ++t) {
+        const double ang = 2.0 * M_PI * t / p->m;
+        tw[t] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    hipStream_t s = p->stream;
+    HIPCHK(hipMemcpyAsync(p->ws + p->off.tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + p->off.pos, p->pos.data(), p->pos.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + p->off.tile_ptr, p->tile_ptr.data(), p->tile_ptr.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+    if (!p->tile_frames.empty())
+        HIPCHK(hipMemcpyAsync(p->ws + p->off.tile_frames, p->tile_frames.data(),
+                              p->tile_frames.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_fill(p->ws + p->off.flag, 16 * sizeof(int), s));
+    HIPCHK(launch_fill(p->ws + p->off.hist, kHistCap * sizeof(float), s));
+    // host vectors are locals: finish the uploads before returning
+    HIPCHK(hipStreamSynchronize(s));
+    return SHARP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument blocks
+// ---------------------------------------------------------------------------
+static FrameArgs frame_args(const sharp_plan_s& p) {
+    FrameArgs A{};
+    A.K = p.K;
+    A.M = p.m;
+    A.nx = p.nx;
+    A.ny = p.ny;
+    A.periodic = p.opt.periodic;
+    A.pos = p.at<int>(p.off.pos);
+    A.tw = p.at<float2>(p.off.tw);
+    A.a = p.at<float>(p.off.a);
+    A.w_g = p.at<float2>(p.off.w_gat);
+    A.w = p.at<float2>(p.off.w_cur);
+    A.psi = p.at<float2>(p.off.psi_v);
+    A.u = p.at<float2>(p.off.u);
+    A.v = p.at<float2>(p.off.v);
+    A.stage = p.m == 256 ? p.at<float2>(p.off.stage) : nullptr;
+    A.resid = p.at<float>(p.off.resid);
+    A.gw_part = p.at<float2>(p.off.gwpart);
+    A.g = p.g;
+    A.beta = 0.75f;
+    return A;
+}
+
+static MergeArgs merge_args(const sharp_plan_s& p) {
+    MergeArgs A{};
+    A.M = p.m;
+    A.nx = p.nx;
+    A.ny = p.ny;
+    A.periodic = p.opt.periodic;
+    A.T = p.T;
+    A.tiles_x = p.tiles_x;
+    A.split = p.split;
+    A.tile_ptr = p.at<int>(p.off.tile_ptr);
+    A.tile_frames = p.at<int>(p.off.tile_frames);
+    A.pos = p.at<int>(p.off.pos);
+    A.v = p.at<float2>(p.off.v);
+    A.u = p.at<float2>(p.off.u);
+    A.w = p.at<float2>(p.off.w_cur);
+    A.Dinv = p.at<float>(p.off.Dinv);
+    A.psi_v_in = p.at<float2>(p.off.psi_v);
+    A.out = p.at<float2>(p.off.psi_v);
+    A.out2 = p.at<float2>(p.off.psi_l);
+    A.D_out = p.at<float>(p.off.D);
+    A.Dinv_out = p.at<float>(p.off.Dinv);
+    A.part = p.at<float4>(p.off.mpart);
+    A.g = p.g;
+    A.eps_D = p.opt.eps_D;
+    return A;
+}
+
+static int density(sharp_plan_s& p) {
+    MergeArgs A = merge_args(p);
+    HIPCHK(launch_merge(MK_DENS, A, p.ntiles, p.stream));
+    return SHARP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// inputs
+// ---------------------------------------------------------------------------
+extern "C" int sharp_set_data(sharp_plan p, const float* d_I) {
+    if (!p || !d_I) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws) return SHARP_ERR_NOT_READY;
+    int blocks = 0;
+    HIPCHK(launch_set_data(d_I, p->at<float>(p->off.a), p->frame_elems(), p->at<float>(p->off.resid),
+                           p->at<int>(p->off.flag), p->stream, &blocks));
+    HIPCHK(launch_reduce(p->at<float>(p->off.resid), blocks, p->at<float>(p->off.scal), p->stream));
+    p->has_data = true;
+    return SHARP_OK;
+}
+
+extern "C" int sharp_set_probe(sharp_plan p, const void* d_w) {
+    if (!p || !d_w) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws) return SHARP_ERR_NOT_READY;
+    const size_t bytes = (size_t)p->m * p->m * sizeof(float2);
+    HIPCHK(launch_copy(p->ws + p->off.w_cur, d_w, bytes, p->stream));
+    HIPCHK(launch_copy(p->ws + p->off.w_gat, d_w, bytes, p->stream));
+    int st = density(*p);
+    if (st) return st;
+    p->has_probe = true;
+    p->has_object = false;
+    return SHARP_OK;
+}
+
+extern "C" int sharp_init_probe(sharp_plan p) {
+    if (!p) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws || !p->has_data) return SHARP_ERR_NOT_READY;
+    hipStream_t s = p->stream;
+    HIPCHK(launch_mean_amp(p->at<float>(p->off.a), p->K, p->m, p->at<float2>(p->off.tmp_w), s));
+    FrameArgs A = frame_args(*p);
+    A.K = 1;
+    A.in = p->at<float2>(p->off.tmp_w);
+    A.out = p->at<float2>(p->off.tmp_w2);
+    HIPCHK(launch_frame(FM_FINV, A, 0, s, nullptr));
+    HIPCHK(launch_roll_probe(p->at<float2>(p->off.tmp_w2), p->m, p->at<float2>(p->off.w_cur),
+                             p->at<float2>(p->off.w_gat), s));
+    int st = density(*p);
+    if (st) return st;
+    p->has_probe = true;
+    p->has_object = false;
+    return SHARP_OK;
+}
+
+extern "C" int sharp_set_object(sharp_plan p, const void* d_psi) {
+    if (!p || !d_psi) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws || !p->has_probe) return SHARP_ERR_NOT_READY;
+    hipStream_t s = p->stream;
+    HIPCHK(launch_copy(p->ws + p->off.psi_v, d_psi, p->obj_elems() * sizeof(float2), s));
+    HIPCHK(launch_fill(p->ws + p->off.u, p->frame_elems() * sizeof(float2), s));
+    HIPCHK(launch_copy(p->ws + p->off.w_gat, p->ws + p->off.w_cur, (size_t)p->m * p->m * sizeof(float2), s));
+    p->g = 1.f;  // z^(0) = Q psi0: carry 0, gather coefficient 1
+    p->iter = 0;
+    p->hist_count = 0;
+    p->gat_stale = false;
+    p->last_probe_updated = false;
+    p->has_object = true;
+    return SHARP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// iteration
+// ---------------------------------------------------------------------------
+static int one_iteration(sharp_plan_s& p, float beta) {
+    hipStream_t s = p.stream;
+    const long long it = p.iter + 1;
+    const bool probe_due = p.opt.probe_every > 0 && it >= p.opt.probe_start &&
+                           (it - p.opt.probe_start) % p.opt.probe_every == 0;
+    FrameArgs A = frame_args(p);
+    A.beta = beta;
+    int blocks = 0;
+    HIPCHK(launch_frame(FM_RAAR, A, 0, s, &blocks));
+    if (p.gat_stale) {
+        HIPCHK(launch_copy(p.ws + p.off.w_gat, p.ws + p.off.w_cur, (size_t)p.m * p.m * sizeof(float2), s));
+        p.gat_stale = false;
+    }
+    HIPCHK(launch_eps(p.at<float>(p.off.resid), blocks, p.at<float>(p.off.scal), p.at<float>(p.off.hist),
+                      (int)(p.hist_count % kHistCap), p.at<int>(p.off.flag), s));
+    p.hist_count++;
+    p.g = beta;
+    MergeArgs Mg = merge_args(p);
+    HIPCHK(launch_merge(probe_due ? MK_VU : MK_V, Mg, p.ntiles, s));
+    if (probe_due) {
+        HIPCHK(launch_probe_partial(p.m, p.K, p.at<int>(p.off.pos), p.nx, p.ny, p.opt.periodic, p.at<float2>(p.off.u),
+                                    p.at<float2>(p.off.w_cur), p.at<float2>(p.off.psi_v), p.at<float2>(p.off.psi_l),
+                                    beta, p.probe_chunks, p.at<float2>(p.off.pnum), p.at<float>(p.off.pden), s));
+        HIPCHK(launch_probe_finish(p.m, p.probe_chunks, p.at<float2>(p.off.pnum), p.at<float>(p.off.pden),
+                                   p.at<float2>(p.off.w_gat), p.at<float2>(p.off.w_cur), s));
+        int st = density(p);
+        if (st) return st;
+        p.gat_stale = true;
+    }
+    p.last_probe_updated = probe_due;
+    p.iter = it;
+    return SHARP_OK;
+}
+
+extern "C" int sharp_raar_iterate(sharp_plan p, int n, float beta) {
+    if (!p || n < 0 || !(beta > 0.f && beta <= 1.f)) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws || !p->has_data || !p->has_probe || !p->has_object) return SHARP_ERR_NOT_READY;
+    for (int l = 0; l < n; ++l) {
+        int st = one_iteration(*p, beta);
+        if (st) return st;
+    }
+    return SHARP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// outputs
+// ---------------------------------------------------------------------------
+extern "C" int sharp_get_object(sharp_plan p, void* d_out) {
+    if (!p || !d_out) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws || !p->has_probe || !p->has_object) return SHARP_ERR_NOT_READY;
+    if (p->last_probe_updated) {
+        HIPCHK(launch_copy(d_out, p->ws + p->off.psi_l, p->obj_elems() * sizeof(float2), p->stream));
+        return SHARP_OK;
+    }
+    MergeArgs A = merge_args(*p);
+    A.out = (float2*)d_out;
+    HIPCHK(launch_merge(MK_U, A, p->ntiles, p->stream));
+    return SHARP_OK;
+}
+
+extern "C" int sharp_get_probe(sharp_plan p, void* d_out) {
+    if (!p || !d_out) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws || !p->has_probe) return SHARP_ERR_NOT_READY;
+    HIPCHK(launch_copy(d_out, p->ws + p->off.w_cur, (size_t)p->m * p->m * sizeof(float2), p->stream));
+    return SHARP_OK;
+}
+
+static int read_flag(sharp_plan_s& p) {
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, p.ws + p.off.flag, sizeof(int), hipMemcpyDeviceToHost, p.stream));
+    HIPCHK(hipStreamSynchronize(p.stream));
+    return flag ? SHARP_ERR_NONFINITE : SHARP_OK;
+}
+
+extern "C" int sharp_sync(sharp_plan p) {
+    if (!p) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws) return SHARP_ERR_NOT_READY;
+    return read_flag(*p);
+}
+
+extern "C" int sharp_get_metrics(sharp_plan p, float* h_eps, int max_n, int* n_written) {
+    if (!p || max_n < 0 || (max_n > 0 && !h_eps)) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws) return SHARP_ERR_NOT_READY;
+    std::vector<float> hist(kHistCap);
+    HIPCHK(hipMemcpyAsync(hist.data(), p->ws + p->off.hist, kHistCap * sizeof(float), hipMemcpyDeviceToHost,
+                          p->stream));
+    int st = read_flag(*p);  // synchronises
+    const long long cnt = std::min<long long>(p->hist_count, kHistCap);
+    const long long start = p->hist_count - cnt;
+    const int nw = (int)std::min<long long>(cnt, max_n);
+    for (int j = 0; j < nw; ++j) h_eps[j] = hist[(start + j) % kHistCap];
+    if (n_written) *n_written = nw;
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// gradient, forward model, operators
+// ---------------------------------------------------------------------------
+extern "C" int sharp_grad(sharp_plan p, const void* d_psi, const void* d_w, float* d_loss, void* d_gpsi,
+                          void* d_gw) {
+    if (!p || !d_psi || !d_w || !d_loss) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws || !p->has_data) return SHARP_ERR_NOT_READY;
+    hipStream_t s = p->stream;
+    FrameArgs A = frame_args(*p);
+    A.psi = (const float2*)d_psi;
+    A.w = (const float2*)d_w;
+    A.w_g = (const float2*)d_w;
+    int blocks = 0;
+    HIPCHK(launch_frame(FM_GRAD, A, p->grad_groups, s, &blocks));
+    HIPCHK(launch_loss(p->at<float>(p->off.resid), p->m == 256 ? p->K * 16 : blocks, d_loss, p->at<int>(p->off.flag), s));
+    if (d_gpsi) {
+        MergeArgs Mg = merge_args(*p);
+        Mg.out = (float2*)d_gpsi;
+        HIPCHK(launch_merge(MK_RAW, Mg, p->ntiles, s));
+    }
+    if (d_gw) {
+        const int slots = frame_partial_slots(p->m, FM_GRAD, blocks);
+        HIPCHK(launch_gw_finish(p->m, slots, p->at<float2>(p->off.gwpart), (float2*)d_gw, s));
+    }
+    return SHARP_OK;
+}
+
+extern "C" int sharp_simulate(sharp_plan p, const void* d_psi, const void* d_w, float* d_I) {
+    if (!p || !d_psi || !d_w || !d_I) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws) return SHARP_ERR_NOT_READY;
+    FrameArgs A = frame_args(*p);
+    A.psi = (const float2*)d_psi;
+    A.w = (const float2*)d_w;
+    A.out_f = d_I;
+    HIPCHK(launch_frame(FM_SIM, A, 0, p->stream, nullptr));
+    return SHARP_OK;
+}
+
+extern "C" int sharp_apply(sharp_plan p, int op, const void* d_in, void* d_out) {
+    if (!p || !d_in || !d_out || d_in == d_out) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws) return SHARP_ERR_NOT_READY;
+    if (op != SHARP_OP_F && op != SHARP_OP_FINV && !p->has_probe) return SHARP_ERR_NOT_READY;
+    if (op == SHARP_OP_PA && !p->has_data) return SHARP_ERR_NOT_READY;
+    hipStream_t s = p->stream;
+    FrameArgs A = frame_args(*p);
+    MergeArgs Mg = merge_args(*p);
+    switch (op) {
+        case SHARP_OP_F:
+        case SHARP_OP_FINV:
+        case SHARP_OP_PA:
+            A.in = (const float2*)d_in;
+            A.out = (float2*)d_out;
+            HIPCHK(launch_frame(op == SHARP_OP_F ? FM_F : op == SHARP_OP_FINV ? FM_FINV : FM_PA, A, 0, s, nullptr));
+            return SHARP_OK;
+        case SHARP_OP_Q:
+            A.psi = (const float2*)d_in;
+            A.out = (float2*)d_out;
+            HIPCHK(launch_frame(FM_Q, A, 0, s, nullptr));
+            return SHARP_OK;
+        case SHARP_OP_QSTAR:
+        case SHARP_OP_OBJECT:
+            Mg.u = (const float2*)d_in;
+            Mg.out = (float2*)d_out;
+            HIPCHK(launch_merge(op == SHARP_OP_QSTAR ? MK_RAWW : MK_OBJ, Mg, p->ntiles, s));
+            return SHARP_OK;
+        case SHARP_OP_PQ:
+            Mg.u = (const float2*)d_in;
+            Mg.out = p->at<float2>(p->off.tmp_obj);
+            HIPCHK(launch_merge(MK_OBJ, Mg, p->ntiles, s));
+            A.psi = p->at<float2>(p->off.tmp_obj);
+            A.out = (float2*)d_out;
+            HIPCHK(launch_frame(FM_Q, A, 0, s, nullptr));
+            return SHARP_OK;
+    }
+    return SHARP_ERR_INVALID_ARG;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoint / resume
+// ---------------------------------------------------------------------------
+namespace {
+struct StateHeader {
+    long long magic, iter, hist_count;
+    int nx, ny, m, K;
+    float g;
+    int gat_stale, last_probe_updated, pad;
+};
+constexpr long long kMagic = 0x5348415250535431LL;
+
+struct StateLayout {
+    size_t u, psi_v, psi_l, w_cur, w_gat, hist, header, total;
+};
+StateLayout state_layout(const sharp_plan_s& p) {
+    StateLayout L{};
+    size_t cur = 0;
+    auto take = [&](size_t b) {
+        size_t at = cur;
+        cur = align_up(cur + b);
+        return at;
+    };
+    const size_t MM = (size_t)p.m * p.m;
+    L.u = take(p.frame_elems() * sizeof(float2));
+    L.psi_v = take(p.obj_elems() * sizeof(float2));
+    L.psi_l = take(p.obj_elems() * sizeof(float2));
+    L.w_cur = take(MM * sizeof(float2));
+    L.w_gat = take(MM * sizeof(float2));
+    L.hist = take(kHistCap * sizeof(float));
+    L.header = take(sizeof(StateHeader));
+    L.total = cur;
+    return L;
+}
+}  // namespace
+
+extern "C" size_t sharp_state_bytes(sharp_plan p) { return p ? state_layout(*p).total : 0; }
+
+extern "C" int sharp_get_state(sharp_plan p, void* d_state) {
+    if (!p || !d_state) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws || !p->has_probe || !p->has_object) return SHARP_ERR_NOT_READY;
+    const StateLayout L = state_layout(*p);
+    char* d = (char*)d_state;
+    hipStream_t s = p->stream;
+    const size_t MM = (size_t)p->m * p->m;
+    HIPCHK(launch_copy(d + L.u, p->ws + p->off.u, p->frame_elems() * sizeof(float2), s));
+    HIPCHK(launch_copy(d + L.psi_v, p->ws + p->off.psi_v, p->obj_elems() * sizeof(float2), s));
+    HIPCHK(launch_copy(d + L.psi_l, p->ws + p->off.psi_l, p->obj_elems() * sizeof(float2), s));
+    HIPCHK(launch_copy(d + L.w_cur, p->ws + p->off.w_cur, MM * sizeof(float2), s));
+    HIPCHK(launch_copy(d + L.w_gat, p->ws + p->off.w_gat, MM * sizeof(float2), s));
+    HIPCHK(launch_copy(d + L.hist, p->ws + p->off.hist, kHistCap * sizeof(float), s));
+    StateHeader h{kMagic, p->iter, p->hist_count, p->nx, p->ny, p->m, p->K, p->g,
+                  p->gat_stale ? 1 : 0, p->last_probe_updated ? 1 : 0, 0};
+    HIPCHK(hipMemcpyAsync(d + L.header, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SHARP_OK;
+}
+
+extern "C" int sharp_set_state(sharp_plan p, const void* d_state) {
+    if (!p || !d_state) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws || !p->has_data) return SHARP_ERR_NOT_READY;
+    const StateLayout L = state_layout(*p);
+    const char* d = (const char*)d_state;
+    hipStream_t s = p->stream;
+    StateHeader h{};
+    HIPCHK(hipMemcpyAsync(&h, d + L.header, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h.magic != kMagic || h.nx != p->nx || h.ny != p->ny || h.m != p->m || h.K != p->K)
+        return SHARP_ERR_INVALID_ARG;
+    const size_t MM = (size_t)p->m * p->m;
+    HIPCHK(launch_copy(p->ws + p->off.u, d + L.u, p->frame_elems() * sizeof(float2), s));
+    HIPCHK(launch_copy(p->ws + p->off.psi_v, d + L.psi_v, p->obj_elems() * sizeof(float2), s));
+    HIPCHK(launch_copy(p->ws + p->off.psi_l, d + L.psi_l, p->obj_elems() * sizeof(float2), s));
+    HIPCHK(launch_copy(p->ws + p->off.w_cur, d + L.w_cur, MM * sizeof(float2), s));
+    HIPCHK(launch_copy(p->ws + p->off.w_gat, d + L.w_gat, MM * sizeof(float2), s));
+    HIPCHK(launch_copy(p->ws + p->off.hist, d + L.hist, kHistCap * sizeof(float), s));
+    p->iter = h.iter;
+    p->hist_count = h.hist_count;
+    p->g = h.g;
+    p->gat_stale = h.gat_stale != 0;
+    p->last_probe_updated = h.last_probe_updated != 0;
+    int st = density(*p);
+    if (st) return st;
+    p->has_probe = true;
+    p->has_object = true;
+    return SHARP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// introspection
+// ---------------------------------------------------------------------------
+extern "C" int sharp_get_plan_info(sharp_plan p, sharp_plan_info* info) {
+    if (!p || !info) return SHARP_ERR_INVALID_ARG;
+    info->nx = p->nx;
+    info->ny = p->ny;
+    info->m = p->m;
+    info->K = p->K;
+    info->periodic = p->opt.periodic;
+    info->tile = p->T;
+    info->tiles_x = p->tiles_x;
+    info->tiles_y = p->tiles_y;
+    info->merge_split = p->split;
+    info->grad_groups = p->grad_groups;
+    info->csr_nnz = (long long)p->tile_frames.size();
+    info->iteration = p->iter;
+    return SHARP_OK;
+}
+
+extern "C" int sharp_get_plan_csr(sharp_plan p, int32_t* h_ptr, int32_t* h_frames) {
+    if (!p || !h_ptr || !h_frames) return SHARP_ERR_INVALID_ARG;
+    std::memcpy(h_ptr, p->tile_ptr.data(), p->tile_ptr.size() * sizeof(int32_t));
+    std::memcpy(h_frames, p->tile_frames.data(), p->tile_frames.size() * sizeof(int32_t));
+    return SHARP_OK;
+}

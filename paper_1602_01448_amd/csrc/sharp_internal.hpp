@@ -1,0 +1,96 @@
+// Internal interfaces between the host plan code (sharp_api.cpp) and the
+// kernels (kernels_frame.hip, kernels_merge.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sharp {
+
+constexpr int kHistCap = 4096;  // eps_a history ring (entries)
+
+// Frame-kernel modes
+enum FrameMode : int {
+    FM_RAAR = 0,  // z = u + g w_g T psi_v; P_a; u' = b z + (1-2b) y; v' = conj(w)(2y - z)
+    FM_PA = 1,    // in -> P_a in
+    FM_GRAD = 2,  // z = w T psi; r = 2 (z - P_a z); v = conj(w) r; gw partial += conj(T psi) r
+    FM_SIM = 3,   // I = |F w T psi|^2
+    FM_F = 4,     // in -> F in
+    FM_FINV = 5,  // in -> F* in
+    FM_Q = 6,     // psi -> w T psi
+};
+
+// Merge-kernel kinds
+enum MergeKind : int {
+    MK_V = 0,     // psi_v = Dinv sum v
+    MK_VU = 1,    // psi_v = Dinv sum v;  psi_l = [Dinv>0] (Dinv sum conj(w) u + g psi_v)
+    MK_U = 2,     // out = [Dinv>0] (Dinv sum conj(w) u + g psi_v)
+    MK_RAW = 3,   // out = sum v
+    MK_RAWW = 4,  // out = sum conj(w) u
+    MK_OBJ = 5,   // out = Dinv sum conj(w) u
+    MK_DENS = 6,  // D = sum |w|^2, Dinv = D > eps ? 1/D : 0
+};
+
+struct FrameArgs {
+    int K, M, nx, ny, periodic;
+    const int* __restrict__ pos;        // [K][2] (y, x)
+    const float2* __restrict__ tw;      // [M] e^{2 pi i t / M}
+    const float* __restrict__ a;        // [K][M][M] amplitudes
+    const float2* __restrict__ w_g;     // gather probe
+    const float2* __restrict__ w;       // current probe
+    const float2* __restrict__ psi;     // gathered object (psi_v, or psi for GRAD/SIM/Q)
+    const float2* __restrict__ in;      // input frames (PA/F/FINV)
+    float2* __restrict__ u;             // carry (RAAR, in/out)
+    float2* __restrict__ v;             // merge input (RAAR, GRAD)
+    float2* __restrict__ out;           // output frames (PA/F/FINV/Q)
+    float* __restrict__ out_f;          // output intensities (SIM)
+    float2* __restrict__ stage;         // multi-pass intermediate [K][M][M]
+    float* __restrict__ resid;          // per-block residual partials
+    float2* __restrict__ gw_part;       // per-block probe-gradient partials
+    float g, beta;
+};
+
+struct MergeArgs {
+    int M, nx, ny, periodic, T, tiles_x, split;
+    const int* __restrict__ tile_ptr;
+    const int* __restrict__ tile_frames;
+    const int* __restrict__ pos;
+    const float2* __restrict__ v;       // frames (pre-multiplied by conj(w))
+    const float2* __restrict__ u;       // frames multiplied by conj(w) on the fly
+    const float2* __restrict__ w;
+    const float* __restrict__ Dinv;
+    const float2* __restrict__ psi_v_in;   // MK_U: g psi_v term
+    float2* __restrict__ out;           // psi_v / out
+    float2* __restrict__ out2;          // psi_l (MK_VU)
+    float* __restrict__ D_out;          // MK_DENS
+    float* __restrict__ Dinv_out;       // MK_DENS
+    float4* __restrict__ part;          // split partials [tiles][split][T*T] (x2 for VU)
+    float g, eps_D;
+};
+
+// launchers (kernels_frame.hip)
+hipError_t launch_frame(int mode, const FrameArgs& a, int grid_hint, hipStream_t s, int* blocks_used);
+int frame_partial_slots(int M, int mode, int blocks);  // gw partial slots per launch
+hipError_t launch_probe_partial(int M, int K, const int* pos, int nx, int ny, int periodic,
+                                const float2* u, const float2* w, const float2* psi_v,
+                                const float2* psi_l, float beta, int chunks, float2* num, float* den,
+                                hipStream_t s);
+hipError_t launch_probe_finish(int M, int chunks, const float2* num, const float* den, float2* w_gat,
+                               float2* w_cur, hipStream_t s);
+hipError_t launch_gw_finish(int M, int slots, const float2* part, float2* gw, hipStream_t s);
+
+// launchers (kernels_merge.hip)
+hipError_t launch_merge(int kind, const MergeArgs& a, int tiles, hipStream_t s);
+hipError_t launch_set_data(const float* I, float* a, size_t n, float* partials, int* flag,
+                           hipStream_t s, int* blocks_used);
+hipError_t launch_reduce(const float* partials, int n, float* out, hipStream_t s);
+hipError_t launch_eps(const float* partials, int n, const float* norm_a2, float* hist, int idx,
+                      int* flag, hipStream_t s);
+hipError_t launch_loss(const float* partials, int n, float* out, int* flag, hipStream_t s);
+hipError_t launch_mean_amp(const float* a, int K, int M, float2* out, hipStream_t s);
+hipError_t launch_roll_probe(const float2* src, int M, float2* w_cur, float2* w_gat, hipStream_t s);
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+}  // namespace sharp

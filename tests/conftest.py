@@ -17,3 +17,19 @@ def pytest_configure(config):
 def rng():
     import numpy as np
     return np.random.default_rng(20160204)
+
+
+def pytest_collection_modifyitems(config, items):
+    """GPU tests need a visible GPU; without one they are skipped (the CPU
+    suite deselects them with -m "not gpu")."""
+    try:
+        import torch
+        have_gpu = torch.cuda.is_available()
+    except Exception:
+        have_gpu = False
+    if have_gpu:
+        return
+    skip = pytest.mark.skip(reason="no GPU visible")
+    for it in items:
+        if "gpu" in it.keywords:
+            it.add_marker(skip)

@@ -1,0 +1,142 @@
+"""Host-side checks of the C ABI (no device work): the library loads and exports
+every symbol declared in include/sharp.h, argument validation, the tile ->
+frame incidence lists and the workspace size."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from sharp_data import gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sharp.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1602_01448_amd._lib import load
+    return load()
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sharp_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    from paper_1602_01448_amd._lib import SIGNATURES
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(n for n, _, _ in SIGNATURES) == names
+
+
+def _create(L, n, m, pos, **kw):
+    from paper_1602_01448_amd._lib import SharpOptions
+    h = ctypes.c_void_p()
+    pos = np.ascontiguousarray(pos, dtype=np.int32)
+    opts = SharpOptions(kw.get("periodic", 0), kw.get("probe_every", 0), kw.get("probe_start", 1),
+                        kw.get("eps_D", 0.0), kw.get("tile", 0), kw.get("merge_split", 0), kw.get("grad_groups", 0))
+    if "reserved" in kw:
+        opts.reserved[0] = kw["reserved"]
+    st = L.sharp_plan_create(ctypes.byref(h), n, n, m, len(pos), pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             ctypes.byref(opts))
+    return st, h
+
+
+def test_status_strings(L):
+    for s in range(-8, 1):
+        assert len(L.sharp_status_string(s)) > 0
+    assert L.sharp_status_string(-99) == b"unknown status"
+
+
+@pytest.mark.parametrize("m,expect", [(16, 0), (32, 0), (64, 0), (128, 0), (256, 0), (48, -2), (8, -2), (512, -2)])
+def test_supported_sizes(L, m, expect):
+    n = max(m, 16) + 8
+    st, h = _create(L, n, m, [(0, 0)])
+    assert st == expect
+    L.sharp_plan_destroy(h)
+
+
+def test_validation(L):
+    assert _create(L, 64, 32, [(0, 0), (33, 0)])[0] == -3      # leaves the object
+    assert _create(L, 64, 32, [(0, -1)])[0] == -3
+    assert _create(L, 64, 32, [(32, 32)])[0] == 0               # last valid corner
+    assert _create(L, 64, 32, [(63, 63)], periodic=1)[0] == 0   # wraps
+    assert _create(L, 64, 32, [(64, 0)], periodic=1)[0] == -3
+    assert _create(L, 16, 32, [(0, 0)])[0] == -2                # m > n
+    assert _create(L, 64, 32, [(0, 0)], tile=24)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], reserved=1)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], eps_D=-1.0)[0] == -1
+    h = ctypes.c_void_p()
+    assert L.sharp_plan_create(ctypes.byref(h), 64, 64, 32, 0, None, None) == -1
+    assert L.sharp_plan_create(None, 64, 64, 32, 1, None, None) == -1
+
+
+def test_calls_before_workspace_are_not_ready(L):
+    st, h = _create(L, 64, 32, [(0, 0), (8, 8)])
+    assert st == 0
+    assert L.sharp_set_data(h, ctypes.c_void_p(16)) == -4
+    assert L.sharp_raar_iterate(h, 1, ctypes.c_float(1.5)) == -1          # beta outside (0, 1]
+    assert L.sharp_raar_iterate(h, 1, ctypes.c_float(0.0)) == -1
+    assert L.sharp_raar_iterate(h, 1, ctypes.c_float(0.75)) == -4
+    assert L.sharp_set_workspace(h, ctypes.c_void_p(256), 16) == -5       # too small (checked first)
+    assert L.sharp_set_workspace(h, ctypes.c_void_p(3), 1 << 40) == -1    # misaligned
+    L.sharp_plan_destroy(h)
+
+
+def _brute_csr(n, m, T, pos, periodic):
+    tiles = (n + T - 1) // T
+    lists = [[] for _ in range(tiles * tiles)]
+    for i, (py, px) in enumerate(pos):
+        hit = set()
+        for ry in range(m):
+            for rx in range(m):
+                y, x = py + ry, px + rx
+                if periodic:
+                    y, x = y % n, x % n
+                hit.add((y // T) * tiles + x // T)
+        for t in sorted(hit):
+            lists[t].append(i)
+    ptr = np.zeros(len(lists) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(l) for l in lists])
+    return ptr, np.array([f for l in lists for f in l], np.int32)
+
+
+@pytest.mark.parametrize("n,m,T,periodic,jit", [(128, 32, 16, 0, 0), (100, 32, 32, 0, 2), (96, 16, 16, 1, 3),
+                                                (200, 64, 64, 1, 5)])
+def test_csr_matches_brute_force(L, n, m, T, periodic, jit):
+    rng = np.random.default_rng(n + m)
+    if periodic:
+        pos = rng.integers(0, n, size=(40, 2)).astype(np.int32)
+    else:
+        pos = gen.raster_positions(5, (n - m) / 4, n, m, jitter=jit, rng=rng)
+    st, h = _create(L, n, m, pos, periodic=periodic, tile=T)
+    assert st == 0
+    from paper_1602_01448_amd._lib import SharpPlanInfo
+    info = SharpPlanInfo()
+    assert L.sharp_get_plan_info(h, ctypes.byref(info)) == 0
+    ptr = np.zeros(info.tiles_x * info.tiles_y + 1, np.int32)
+    fr = np.zeros(info.csr_nnz, np.int32)
+    P = ctypes.POINTER(ctypes.c_int32)
+    assert L.sharp_get_plan_csr(h, ptr.ctypes.data_as(P), fr.ctypes.data_as(P)) == 0
+    bptr, bfr = _brute_csr(n, m, T, pos, periodic)
+    assert np.array_equal(ptr, bptr) and np.array_equal(fr, bfr)
+    L.sharp_plan_destroy(h)
+
+
+def test_workspace_grows_with_frames(L):
+    sizes = []
+    for K in (10, 20, 40):
+        pos = np.zeros((K, 2), np.int32)
+        st, h = _create(L, 256, 64, pos)
+        sizes.append(L.sharp_workspace_bytes(h))
+        # frame stacks a (4 B), u (8 B), v (8 B) per pixel at least
+        assert sizes[-1] >= K * 64 * 64 * 20
+        assert sizes[-1] % 256 == 0
+        L.sharp_plan_destroy(h)
+    assert sizes[0] < sizes[1] < sizes[2]
