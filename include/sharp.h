@@ -206,6 +206,19 @@ int sharp_get_plan_info(sharp_plan plan, sharp_plan_info* info);
 int sharp_get_plan_csr(sharp_plan plan, int32_t* h_ptr, int32_t* h_frames);
 
 /* ------------------------------------------------------------------------
+ * Kernel timing (diagnostics).  While enabled, the launches of
+ * sharp_raar_iterate and sharp_grad are bracketed by HIP events on the
+ * plan's stream, per category: 0 frame kernel (m <= 128: the whole fused
+ * kernel; m = 256: the row pass with the gather), 1 column pass (m = 256),
+ * 2 output row pass (m = 256), 3 merge, 4 residual reduction, 5 probe
+ * update, 6 copies.  sharp_timing_read synchronises, adds the elapsed
+ * milliseconds and launch counts of the finished pairs into h_ms[8] and
+ * h_launches[8] (overwritten) and forgets them.
+ * ---------------------------------------------------------------------- */
+int sharp_timing_enable(sharp_plan plan, int on);
+int sharp_timing_read(sharp_plan plan, double* h_ms, long long* h_launches);
+
+/* ------------------------------------------------------------------------
  * Batched execution of independent plans (one launch sequence per
  * iteration, all scans together).  Each plan keeps its own state and must
  * have data, probe and object set; the plans' streams are ignored and the

@@ -8,3 +8,4 @@ pointers and sizes across the C ABI.
 from ._lib import OPS, SharpError, load  # noqa: F401
 from .plan import Plan  # noqa: F401
 from .autograd import AmplitudeLoss  # noqa: F401
+from .batch import Batch  # noqa: F401

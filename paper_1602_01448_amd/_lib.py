@@ -69,6 +69,8 @@ SIGNATURES = [
     ("sharp_set_state", c_int, [c_void_p, c_void_p]),
     ("sharp_get_plan_info", c_int, [c_void_p, POINTER(SharpPlanInfo)]),
     ("sharp_get_plan_csr", c_int, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    ("sharp_timing_enable", c_int, [c_void_p, c_int]),
+    ("sharp_timing_read", c_int, [c_void_p, POINTER(ctypes.c_double), POINTER(c_longlong)]),
     ("sharp_batch_create", c_int, [POINTER(c_void_p), c_int, POINTER(c_void_p)]),
     ("sharp_batch_destroy", None, [c_void_p]),
     ("sharp_batch_workspace_bytes", c_size_t, [c_void_p]),

@@ -207,6 +207,76 @@ __device__ __forceinline__ void fft_1d_post(float2* lds, const float2* twl, P& p
     }
 }
 
+// One group of G frames: prologue -> F -> Fourier op -> F* -> epilogue.
+// Ends with a barrier, so the caller may reuse the LDS right away.
+template <int M, int MODE>
+__device__ __forceinline__ void fg_group(const FrameArgs& A, int grp, float2* lds, const float2* twl, float& resid,
+                                         float2* gacc) {
+    using C = FG<M>;
+    constexpr int NT = C::NT, G = C::G, NP = C::NP, MM = M * M;
+    float2 z[2 * NP], t[2 * NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int f = e0 / MM, rem = e0 % MM, y = rem / M, x = rem % M;
+        const int frame = grp * G + f;
+        z[2 * k] = z[2 * k + 1] = t[2 * k] = t[2 * k + 1] = make_float2(0.f, 0.f);
+        if (frame < A.K)
+            prologue2<MODE>(A, frame, y, x, (size_t)frame * MM + rem, rem, z[2 * k], z[2 * k + 1], t[2 * k],
+                            t[2 * k + 1]);
+        lds[pidx(e0)] = z[2 * k];
+        lds[pidx(e0 + 1)] = z[2 * k + 1];
+    }
+    __syncthreads();
+
+    constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
+    NoPost none;
+    fft_1d<M, D1, NT, G * M, RowLay<M>>(lds, twl, none);
+    FGPost<M, MODE> post{{A.a, A.out_f, 0.f}, grp * G, A.K};
+    fft_1d_post<M, D1, NT, G * M, ColLayFG<M>>(lds, twl, post);
+    resid += post.op.resid;
+    if constexpr (MODE == FM_SIM) return;
+    if constexpr (MODE == FM_F || MODE == FM_FINV) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (threadIdx.x + NT * k);
+            const int f = e0 / MM, rem = e0 % MM, frame = grp * G + f;
+            if (frame < A.K) st2(A.out, (size_t)frame * MM + rem, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+        }
+        __syncthreads();
+        return;
+    }
+    fft_1d<M, -1, NT, G * M, RowLay<M>>(lds, twl, none);
+    fft_1d<M, -1, NT, G * M, ColLayFG<M>>(lds, twl, none);
+    const float inv_m = 1.0f / M;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int f = e0 / MM, rem = e0 % MM, frame = grp * G + f;
+        if (frame >= A.K) continue;
+        const size_t gi = (size_t)frame * MM + rem;
+        const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
+        if constexpr (MODE == FM_RAAR) {
+            float2 w0, w1;
+            ld2(A.w, rem, w0, w1);
+            const float b = A.beta, c = 1.f - 2.f * A.beta;
+            st2(A.u, gi, cadd(cscale(z[2 * k], b), cscale(y0, c)), cadd(cscale(z[2 * k + 1], b), cscale(y1, c)));
+            st2(A.v, gi, cconjmul(w0, csub(cscale(y0, 2.f), z[2 * k])),
+                cconjmul(w1, csub(cscale(y1, 2.f), z[2 * k + 1])));
+        } else if constexpr (MODE == FM_PA) {
+            st2(A.out, gi, y0, y1);
+        } else if constexpr (MODE == FM_GRAD) {
+            float2 w0, w1;
+            ld2(A.w, rem, w0, w1);
+            const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
+            st2(A.v, gi, cconjmul(w0, r0), cconjmul(w1, r1));
+            gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t[2 * k], r0));
+            gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t[2 * k + 1], r1));
+        }
+    }
+    __syncthreads();
+}
+
 template <int M, int MODE>
 __global__ void __launch_bounds__(FG<M>::NT) fg_kernel(FrameArgs A) {
     using C = FG<M>;
@@ -223,74 +293,7 @@ __global__ void __launch_bounds__(FG<M>::NT) fg_kernel(FrameArgs A) {
     for (int i = 0; i < 2 * NP; ++i) gacc[i] = make_float2(0.f, 0.f);
 
     const int ngroups = (A.K + G - 1) / G;
-    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-        float2 z[2 * NP], t[2 * NP];
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int f = e0 / MM, rem = e0 % MM, y = rem / M, x = rem % M;
-            const int frame = grp * G + f;
-            z[2 * k] = z[2 * k + 1] = t[2 * k] = t[2 * k + 1] = make_float2(0.f, 0.f);
-            if (frame < A.K)
-                prologue2<MODE>(A, frame, y, x, (size_t)frame * MM + rem, rem, z[2 * k], z[2 * k + 1],
-                                t[2 * k], t[2 * k + 1]);
-            if constexpr (MODE == FM_Q) {
-                if (frame < A.K) st2(A.out, (size_t)frame * MM + rem, z[2 * k], z[2 * k + 1]);
-            } else {
-                lds[pidx(e0)] = z[2 * k];
-                lds[pidx(e0 + 1)] = z[2 * k + 1];
-            }
-        }
-        if constexpr (MODE == FM_Q) continue;
-        __syncthreads();
-
-        constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
-        NoPost none;
-        fft_1d<M, D1, NT, G * M, RowLay<M>>(lds, twl, none);
-        FGPost<M, MODE> post{{A.a, A.out_f, 0.f}, grp * G, A.K};
-        fft_1d_post<M, D1, NT, G * M, ColLayFG<M>>(lds, twl, post);
-        resid += post.op.resid;
-        if constexpr (MODE == FM_SIM) continue;
-        if constexpr (MODE == FM_F || MODE == FM_FINV) {
-#pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                const int e0 = 2 * (threadIdx.x + NT * k);
-                const int f = e0 / MM, rem = e0 % MM, frame = grp * G + f;
-                if (frame < A.K) st2(A.out, (size_t)frame * MM + rem, lds[pidx(e0)], lds[pidx(e0 + 1)]);
-            }
-            __syncthreads();
-            continue;
-        }
-        fft_1d<M, -1, NT, G * M, RowLay<M>>(lds, twl, none);
-        fft_1d<M, -1, NT, G * M, ColLayFG<M>>(lds, twl, none);
-        const float inv_m = 1.0f / M;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int f = e0 / MM, rem = e0 % MM, frame = grp * G + f;
-            if (frame >= A.K) continue;
-            const size_t gi = (size_t)frame * MM + rem;
-            const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
-            if constexpr (MODE == FM_RAAR) {
-                float2 w0, w1;
-                ld2(A.w, rem, w0, w1);
-                const float b = A.beta, c = 1.f - 2.f * A.beta;
-                st2(A.u, gi, cadd(cscale(z[2 * k], b), cscale(y0, c)), cadd(cscale(z[2 * k + 1], b), cscale(y1, c)));
-                st2(A.v, gi, cconjmul(w0, csub(cscale(y0, 2.f), z[2 * k])),
-                    cconjmul(w1, csub(cscale(y1, 2.f), z[2 * k + 1])));
-            } else if constexpr (MODE == FM_PA) {
-                st2(A.out, gi, y0, y1);
-            } else if constexpr (MODE == FM_GRAD) {
-                float2 w0, w1;
-                ld2(A.w, rem, w0, w1);
-                const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
-                st2(A.v, gi, cconjmul(w0, r0), cconjmul(w1, r1));
-                gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t[2 * k], r0));
-                gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t[2 * k + 1], r1));
-            }
-        }
-        __syncthreads();
-    }
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) fg_group<M, MODE>(A, grp, lds, twl, resid, gacc);
     if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
         const float s = block_sum(resid, red);
         if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
@@ -313,43 +316,48 @@ struct MP {
     static constexpr int NT = 256, E = 16, NP = E / 2;
     static constexpr int RB = NT * E / M;  // rows per row-pass workgroup
     static constexpr int CB = NT * E / M;  // columns per column-pass workgroup
+    static constexpr int NRB = M / RB, NCB = M / CB;
     static constexpr int LDS = pidx(NT * E);
     static constexpr size_t SMEM = (size_t)(LDS + M) * sizeof(float2);
 };
 
-// Row pass forward: prologue + row FFTs -> stage
+// Row pass forward on item it = frame * NRB + row block: prologue + row FFTs -> stage
+template <int M, int MODE>
+__device__ __forceinline__ void mp_row_fwd_item(const FrameArgs& A, int it, float2* lds, const float2* twl) {
+    using C = MP<M>;
+    constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = C::NRB;
+    const int frame = it / NRB, rb = it % NRB;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int y = rb * RB + e0 / M, x = e0 % M, rem = y * M + x;
+        float2 z0, z1, t0, t1;
+        prologue2<MODE>(A, frame, y, x, (size_t)frame * MM + rem, rem, z0, z1, t0, t1);
+        lds[pidx(e0)] = z0;
+        lds[pidx(e0 + 1)] = z1;
+    }
+    __syncthreads();
+    constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
+    NoPost none;
+    fft_1d<M, D1, NT, RB, RowLay<M>>(lds, twl, none);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int y = rb * RB + e0 / M, x = e0 % M;
+        st2(A.stage, (size_t)frame * MM + y * M + x, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+    }
+    __syncthreads();
+}
+
 template <int M, int MODE>
 __global__ void __launch_bounds__(256) mp_row_fwd(FrameArgs A) {
     using C = MP<M>;
-    constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = M / RB;
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* twl = smem + C::LDS;
-    for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
-    const int items = A.K * NRB;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) {
-        const int frame = it / NRB, rb = it % NRB;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int y = rb * RB + e0 / M, x = e0 % M, rem = y * M + x;
-            float2 z0, z1, t0, t1;
-            prologue2<MODE>(A, frame, y, x, (size_t)frame * MM + rem, rem, z0, z1, t0, t1);
-            lds[pidx(e0)] = z0;
-            lds[pidx(e0 + 1)] = z1;
-        }
-        __syncthreads();
-        constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
-        NoPost none;
-        fft_1d<M, D1, NT, RB, RowLay<M>>(lds, twl, none);
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int y = rb * RB + e0 / M, x = e0 % M;
-            st2(A.stage, (size_t)frame * MM + y * M + x, lds[pidx(e0)], lds[pidx(e0 + 1)]);
-        }
-        __syncthreads();
-    }
+    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = A.tw[t];
+    const int items = A.K * C::NRB;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) mp_row_fwd_item<M, MODE>(A, it, lds, twl);
 }
 
 template <int M, int MODE>
@@ -363,62 +371,115 @@ struct CBPost {
     }
 };
 
-// Column pass: column FFTs + Fourier op (+ inverse column FFTs)
+// Column pass on item it = frame * NCB + column block: column FFTs + Fourier op
+// (+ inverse column FFTs); returns this thread's residual contribution.
+template <int M, int MODE>
+__device__ __forceinline__ float mp_col_item(const FrameArgs& A, int it, float2* lds, const float2* twl) {
+    using C = MP<M>;
+    constexpr int NT = C::NT, NP = C::NP, CB = C::CB, MM = M * M, NCB = C::NCB;
+    const int frame = it / NCB, cb = it % NCB;
+    const size_t fb = (size_t)frame * MM;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int y = e0 / CB, c = e0 % CB;
+        float2 a0, a1;
+        ld2(A.stage, fb + (size_t)y * M + cb * CB + c, a0, a1);
+        lds[pidx(e0)] = a0;
+        lds[pidx(e0 + 1)] = a1;
+    }
+    __syncthreads();
+    constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
+    CBPost<M, MODE> post{{A.a, A.out_f, 0.f}, fb, cb * CB};
+    fft_1d_post<M, D1, NT, CB, ColLayCB<CB>>(lds, twl, post);
+    if constexpr (MODE == FM_SIM) return post.op.resid;
+    float2* dst = A.stage;
+    if constexpr (MODE == FM_F || MODE == FM_FINV) {
+        dst = A.out;
+    } else {
+        NoPost none;
+        fft_1d<M, -1, NT, CB, ColLayCB<CB>>(lds, twl, none);
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int y = e0 / CB, c = e0 % CB;
+        st2(dst, fb + (size_t)y * M + cb * CB + c, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+    }
+    __syncthreads();
+    return post.op.resid;
+}
+
 template <int M, int MODE>
 __global__ void __launch_bounds__(256) mp_col(FrameArgs A) {
     using C = MP<M>;
-    constexpr int NT = C::NT, NP = C::NP, CB = C::CB, MM = M * M, NCB = M / CB;
     extern __shared__ float2 smem[];
-    __shared__ float red[NT / 64];
+    __shared__ float red[C::NT / 64];
     float2* lds = smem;
     float2* twl = smem + C::LDS;
-    for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
+    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = A.tw[t];
     float resid = 0.f;
-    const int items = A.K * NCB;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) {
-        const int frame = it / NCB, cb = it % NCB;
-        const size_t fb = (size_t)frame * MM;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int y = e0 / CB, c = e0 % CB;
-            float2 a0, a1;
-            ld2(A.stage, fb + (size_t)y * M + cb * CB + c, a0, a1);
-            lds[pidx(e0)] = a0;
-            lds[pidx(e0 + 1)] = a1;
-        }
-        __syncthreads();
-        constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
-        CBPost<M, MODE> post{{A.a, A.out_f, 0.f}, fb, cb * CB};
-        fft_1d_post<M, D1, NT, CB, ColLayCB<CB>>(lds, twl, post);
-        resid += post.op.resid;
-        if constexpr (MODE == FM_SIM) continue;
-        float2* dst = A.stage;
-        if constexpr (MODE == FM_F || MODE == FM_FINV) {
-            dst = A.out;
-        } else {
-            NoPost none;
-            fft_1d<M, -1, NT, CB, ColLayCB<CB>>(lds, twl, none);
-        }
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int y = e0 / CB, c = e0 % CB;
-            st2(dst, fb + (size_t)y * M + cb * CB + c, lds[pidx(e0)], lds[pidx(e0 + 1)]);
-        }
-        __syncthreads();
-    }
+    const int items = A.K * C::NCB;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) resid += mp_col_item<M, MODE>(A, it, lds, twl);
     if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
         const float s = block_sum(resid, red);
         if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
     }
 }
 
-// Row pass inverse: inverse row FFTs + epilogue
+// Row pass inverse on item it: inverse row FFTs + epilogue
+template <int M, int MODE>
+__device__ __forceinline__ void mp_row_inv_item(const FrameArgs& A, int it, float2* lds, const float2* twl,
+                                                float2* gacc) {
+    using C = MP<M>;
+    constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = C::NRB;
+    const int frame = it / NRB, rb = it % NRB;
+    const size_t fb = (size_t)frame * MM;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int y = rb * RB + e0 / M, x = e0 % M;
+        float2 a0, a1;
+        ld2(A.stage, fb + (size_t)y * M + x, a0, a1);
+        lds[pidx(e0)] = a0;
+        lds[pidx(e0 + 1)] = a1;
+    }
+    __syncthreads();
+    NoPost none;
+    fft_1d<M, -1, NT, RB, RowLay<M>>(lds, twl, none);
+    const float inv_m = 1.0f / M;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int y = rb * RB + e0 / M, x = e0 % M, rem = y * M + x;
+        const size_t gi = fb + rem;
+        const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
+        if constexpr (MODE == FM_RAAR) {
+            float2 z0, z1, t0, t1, w0, w1;
+            prologue2<MODE>(A, frame, y, x, gi, rem, z0, z1, t0, t1);
+            ld2(A.w, rem, w0, w1);
+            const float b = A.beta, c = 1.f - 2.f * A.beta;
+            st2(A.u, gi, cadd(cscale(z0, b), cscale(y0, c)), cadd(cscale(z1, b), cscale(y1, c)));
+            st2(A.v, gi, cconjmul(w0, csub(cscale(y0, 2.f), z0)), cconjmul(w1, csub(cscale(y1, 2.f), z1)));
+        } else if constexpr (MODE == FM_PA) {
+            st2(A.out, gi, y0, y1);
+        } else if constexpr (MODE == FM_GRAD) {
+            float2 t0, t1, w0, w1;
+            gather2(A, frame, y, x, t0, t1);
+            ld2(A.w, rem, w0, w1);
+            const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
+            st2(A.v, gi, cconjmul(w0, r0), cconjmul(w1, r1));
+            gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t0, r0));
+            gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t1, r1));
+        }
+    }
+    __syncthreads();
+}
+
 template <int M, int MODE>
 __global__ void __launch_bounds__(256) mp_row_inv(FrameArgs A) {
     using C = MP<M>;
-    constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = M / RB;
+    constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = C::NRB;
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* twl = smem + C::LDS;
@@ -427,57 +488,14 @@ __global__ void __launch_bounds__(256) mp_row_inv(FrameArgs A) {
 #pragma unroll
     for (int i = 0; i < 2 * NP; ++i) gacc[i] = make_float2(0.f, 0.f);
     const int items = A.K * NRB;
-    int rb_fixed = blockIdx.x % NRB;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) {
-        const int frame = it / NRB, rb = it % NRB;
-        const size_t fb = (size_t)frame * MM;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) mp_row_inv_item<M, MODE>(A, it, lds, twl, gacc);
+    if constexpr (MODE == FM_GRAD) {
+        // gridDim.x is a multiple of NRB, so this block only saw row block blockIdx.x % NRB.
+        const int slot = blockIdx.x / NRB, rb = blockIdx.x % NRB;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const int e0 = 2 * (threadIdx.x + NT * k);
             const int y = rb * RB + e0 / M, x = e0 % M;
-            float2 a0, a1;
-            ld2(A.stage, fb + (size_t)y * M + x, a0, a1);
-            lds[pidx(e0)] = a0;
-            lds[pidx(e0 + 1)] = a1;
-        }
-        __syncthreads();
-        NoPost none;
-        fft_1d<M, -1, NT, RB, RowLay<M>>(lds, twl, none);
-        const float inv_m = 1.0f / M;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int y = rb * RB + e0 / M, x = e0 % M, rem = y * M + x;
-            const size_t gi = fb + rem;
-            const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
-            if constexpr (MODE == FM_RAAR) {
-                float2 z0, z1, t0, t1, w0, w1;
-                prologue2<MODE>(A, frame, y, x, gi, rem, z0, z1, t0, t1);
-                ld2(A.w, rem, w0, w1);
-                const float b = A.beta, c = 1.f - 2.f * A.beta;
-                st2(A.u, gi, cadd(cscale(z0, b), cscale(y0, c)), cadd(cscale(z1, b), cscale(y1, c)));
-                st2(A.v, gi, cconjmul(w0, csub(cscale(y0, 2.f), z0)), cconjmul(w1, csub(cscale(y1, 2.f), z1)));
-            } else if constexpr (MODE == FM_PA) {
-                st2(A.out, gi, y0, y1);
-            } else if constexpr (MODE == FM_GRAD) {
-                float2 t0, t1, w0, w1;
-                gather2(A, frame, y, x, t0, t1);
-                ld2(A.w, rem, w0, w1);
-                const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
-                st2(A.v, gi, cconjmul(w0, r0), cconjmul(w1, r1));
-                gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t0, r0));
-                gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t1, r1));
-            }
-        }
-        __syncthreads();
-    }
-    if constexpr (MODE == FM_GRAD) {
-        // gridDim.x is a multiple of NRB, so this block only saw row block rb_fixed.
-        const int slot = blockIdx.x / NRB;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int y = rb_fixed * RB + e0 / M, x = e0 % M;
             st2(A.gw_part, (size_t)slot * MM + y * M + x, gacc[2 * k], gacc[2 * k + 1]);
         }
     }
@@ -502,8 +520,10 @@ __global__ void __launch_bounds__(256) q_kernel(FrameArgs A) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+static const Timer kNoTimer{};
+
 template <int M, int MODE>
-static hipError_t launch_fg(const FrameArgs& A, int grid, hipStream_t s) {
+static hipError_t launch_fg(const FrameArgs& A, int grid, hipStream_t s, const Timer& t) {
     using C = FG<M>;
     auto k = fg_kernel<M, MODE>;
     static bool attr = false;
@@ -512,22 +532,33 @@ static hipError_t launch_fg(const FrameArgs& A, int grid, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr = true;
     }
+    t.begin(TC_FRAME);
     hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), C::SMEM, s, A);
+    t.end(TC_FRAME);
     return hipGetLastError();
 }
 
 template <int M, int MODE>
-static hipError_t launch_mp(const FrameArgs& A, int grid_rows, int grid_cols, int grid_inv, hipStream_t s) {
+static hipError_t launch_mp(const FrameArgs& A, int grid_rows, int grid_cols, int grid_inv, hipStream_t s,
+                            const Timer& t) {
     using C = MP<M>;
+    t.begin(TC_FRAME);
     hipLaunchKernelGGL((mp_row_fwd<M, MODE>), dim3(grid_rows), dim3(C::NT), C::SMEM, s, A);
+    t.end(TC_FRAME);
+    t.begin(TC_COLS);
     hipLaunchKernelGGL((mp_col<M, MODE>), dim3(grid_cols), dim3(C::NT), C::SMEM, s, A);
-    if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD)
+    t.end(TC_COLS);
+    if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
+        t.begin(TC_FRAME_OUT);
         hipLaunchKernelGGL((mp_row_inv<M, MODE>), dim3(grid_inv), dim3(C::NT), C::SMEM, s, A);
+        t.end(TC_FRAME_OUT);
+    }
     return hipGetLastError();
 }
 
 template <int M>
-static hipError_t dispatch_m(int mode, const FrameArgs& A, int grid_hint, hipStream_t s, int* blocks_used) {
+static hipError_t dispatch_m(int mode, const FrameArgs& A, int grid_hint, hipStream_t s, int* blocks_used,
+                             const Timer& t) {
     if (mode == FM_Q) {
         const size_t npairs = (size_t)A.K * M * M / 2;
         int grid = (int)std::min<size_t>((npairs + 255) / 256, 65536);
@@ -542,12 +573,12 @@ static hipError_t dispatch_m(int mode, const FrameArgs& A, int grid_hint, hipStr
         if (mode == FM_GRAD && grid_hint > 0) grid = std::min(ngroups, grid_hint);
         if (blocks_used) *blocks_used = grid;
         switch (mode) {
-            case FM_RAAR: return launch_fg<M, FM_RAAR>(A, grid, s);
-            case FM_PA: return launch_fg<M, FM_PA>(A, grid, s);
-            case FM_GRAD: return launch_fg<M, FM_GRAD>(A, grid, s);
-            case FM_SIM: return launch_fg<M, FM_SIM>(A, grid, s);
-            case FM_F: return launch_fg<M, FM_F>(A, grid, s);
-            case FM_FINV: return launch_fg<M, FM_FINV>(A, grid, s);
+            case FM_RAAR: return launch_fg<M, FM_RAAR>(A, grid, s, t);
+            case FM_PA: return launch_fg<M, FM_PA>(A, grid, s, t);
+            case FM_GRAD: return launch_fg<M, FM_GRAD>(A, grid, s, t);
+            case FM_SIM: return launch_fg<M, FM_SIM>(A, grid, s, t);
+            case FM_F: return launch_fg<M, FM_F>(A, grid, s, t);
+            case FM_FINV: return launch_fg<M, FM_FINV>(A, grid, s, t);
         }
         return hipErrorInvalidValue;
     } else {
@@ -560,24 +591,26 @@ static hipError_t dispatch_m(int mode, const FrameArgs& A, int grid_hint, hipStr
         }
         if (blocks_used) *blocks_used = (mode == FM_GRAD) ? ginv : items;
         switch (mode) {
-            case FM_RAAR: return launch_mp<M, FM_RAAR>(A, items, items, ginv, s);
-            case FM_PA: return launch_mp<M, FM_PA>(A, items, items, ginv, s);
-            case FM_GRAD: return launch_mp<M, FM_GRAD>(A, items, items, ginv, s);
-            case FM_SIM: return launch_mp<M, FM_SIM>(A, items, items, ginv, s);
-            case FM_F: return launch_mp<M, FM_F>(A, items, items, ginv, s);
-            case FM_FINV: return launch_mp<M, FM_FINV>(A, items, items, ginv, s);
+            case FM_RAAR: return launch_mp<M, FM_RAAR>(A, items, items, ginv, s, t);
+            case FM_PA: return launch_mp<M, FM_PA>(A, items, items, ginv, s, t);
+            case FM_GRAD: return launch_mp<M, FM_GRAD>(A, items, items, ginv, s, t);
+            case FM_SIM: return launch_mp<M, FM_SIM>(A, items, items, ginv, s, t);
+            case FM_F: return launch_mp<M, FM_F>(A, items, items, ginv, s, t);
+            case FM_FINV: return launch_mp<M, FM_FINV>(A, items, items, ginv, s, t);
         }
         return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_frame(int mode, const FrameArgs& A, int grid_hint, hipStream_t s, int* blocks_used) {
+hipError_t launch_frame(int mode, const FrameArgs& A, int grid_hint, hipStream_t s, int* blocks_used,
+                        const Timer* tp) {
+    const Timer& t = tp ? *tp : kNoTimer;
     switch (A.M) {
-        case 16: return dispatch_m<16>(mode, A, grid_hint, s, blocks_used);
-        case 32: return dispatch_m<32>(mode, A, grid_hint, s, blocks_used);
-        case 64: return dispatch_m<64>(mode, A, grid_hint, s, blocks_used);
-        case 128: return dispatch_m<128>(mode, A, grid_hint, s, blocks_used);
-        case 256: return dispatch_m<256>(mode, A, grid_hint, s, blocks_used);
+        case 16: return dispatch_m<16>(mode, A, grid_hint, s, blocks_used, t);
+        case 32: return dispatch_m<32>(mode, A, grid_hint, s, blocks_used, t);
+        case 64: return dispatch_m<64>(mode, A, grid_hint, s, blocks_used, t);
+        case 128: return dispatch_m<128>(mode, A, grid_hint, s, blocks_used, t);
+        case 256: return dispatch_m<256>(mode, A, grid_hint, s, blocks_used, t);
     }
     return hipErrorInvalidValue;
 }
@@ -673,6 +706,107 @@ hipError_t launch_probe_finish(int M, int chunks, const float2* num, const float
 
 hipError_t launch_gw_finish(int M, int slots, const float2* part, float2* gw, hipStream_t s) {
     hipLaunchKernelGGL(gw_finish_kernel, dim3((M * M + 255) / 256), dim3(256), 0, s, M * M, slots, part, gw);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched execution: items (scan, local item) over a device table of scans.
+// Each item runs exactly the arithmetic of the single-scan kernels and writes
+// its residual partial where the single-scan launch (one item per block)
+// would, so a batched iteration reproduces the single-scan one bit for bit.
+// The grid is sized to the resident capacity and strides over the item list.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(FG<M>::NT) batch_fg_kernel(const FrameArgs* __restrict__ D,
+                                                             const int2* __restrict__ items, int n) {
+    using C = FG<M>;
+    extern __shared__ float2 smem[];
+    __shared__ float red[C::NT / 64];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    if (n <= 0) return;
+    const float2* tw = D[items[0].x].tw;  // identical table for every scan of this frame size
+    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = tw[t];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        const FrameArgs A = D[w.x];
+        float resid = 0.f;
+        fg_group<M, FM_RAAR>(A, w.y, lds, twl, resid, nullptr);
+        const float s = block_sum(resid, red);
+        if (threadIdx.x == 0) A.resid[w.y] = s;
+    }
+}
+
+template <int M, int PHASE>
+__global__ void __launch_bounds__(256) batch_mp_kernel(const FrameArgs* __restrict__ D, const int2* __restrict__ items,
+                                                       int n) {
+    using C = MP<M>;
+    extern __shared__ float2 smem[];
+    __shared__ float red[C::NT / 64];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    if (n <= 0) return;
+    const float2* tw = D[items[0].x].tw;
+    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = tw[t];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        const FrameArgs A = D[w.x];
+        if constexpr (PHASE == 0) {
+            mp_row_fwd_item<M, FM_RAAR>(A, w.y, lds, twl);
+        } else if constexpr (PHASE == 1) {
+            const float s = block_sum(mp_col_item<M, FM_RAAR>(A, w.y, lds, twl), red);
+            if (threadIdx.x == 0) A.resid[w.y] = s;
+        } else {
+            mp_row_inv_item<M, FM_RAAR>(A, w.y, lds, twl, nullptr);
+        }
+    }
+}
+
+template <class K>
+static int occupancy(K k, int threads, size_t smem) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, threads, smem) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <int M>
+static hipError_t prep_batch_fg() {
+    return hipFuncSetAttribute((const void*)batch_fg_kernel<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)FG<M>::SMEM);
+}
+
+hipError_t batch_frame_prepare(int M, int phase, int* blocks_per_cu) {
+    hipError_t e = hipSuccess;
+    switch (M) {
+        case 16: e = prep_batch_fg<16>(); *blocks_per_cu = occupancy(batch_fg_kernel<16>, FG<16>::NT, FG<16>::SMEM); break;
+        case 32: e = prep_batch_fg<32>(); *blocks_per_cu = occupancy(batch_fg_kernel<32>, FG<32>::NT, FG<32>::SMEM); break;
+        case 64: e = prep_batch_fg<64>(); *blocks_per_cu = occupancy(batch_fg_kernel<64>, FG<64>::NT, FG<64>::SMEM); break;
+        case 128: e = prep_batch_fg<128>(); *blocks_per_cu = occupancy(batch_fg_kernel<128>, FG<128>::NT, FG<128>::SMEM); break;
+        case 256:
+            if (phase == 0) *blocks_per_cu = occupancy(batch_mp_kernel<256, 0>, 256, MP<256>::SMEM);
+            else if (phase == 1) *blocks_per_cu = occupancy(batch_mp_kernel<256, 1>, 256, MP<256>::SMEM);
+            else *blocks_per_cu = occupancy(batch_mp_kernel<256, 2>, 256, MP<256>::SMEM);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return e;
+}
+
+hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* items, int n, int grid,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (M) {
+        case 16: hipLaunchKernelGGL(batch_fg_kernel<16>, dim3(grid), dim3(FG<16>::NT), FG<16>::SMEM, s, D, items, n); break;
+        case 32: hipLaunchKernelGGL(batch_fg_kernel<32>, dim3(grid), dim3(FG<32>::NT), FG<32>::SMEM, s, D, items, n); break;
+        case 64: hipLaunchKernelGGL(batch_fg_kernel<64>, dim3(grid), dim3(FG<64>::NT), FG<64>::SMEM, s, D, items, n); break;
+        case 128: hipLaunchKernelGGL(batch_fg_kernel<128>, dim3(grid), dim3(FG<128>::NT), FG<128>::SMEM, s, D, items, n); break;
+        case 256:
+            if (phase == 0) hipLaunchKernelGGL((batch_mp_kernel<256, 0>), dim3(grid), dim3(256), MP<256>::SMEM, s, D, items, n);
+            else if (phase == 1) hipLaunchKernelGGL((batch_mp_kernel<256, 1>), dim3(grid), dim3(256), MP<256>::SMEM, s, D, items, n);
+            else hipLaunchKernelGGL((batch_mp_kernel<256, 2>), dim3(grid), dim3(256), MP<256>::SMEM, s, D, items, n);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

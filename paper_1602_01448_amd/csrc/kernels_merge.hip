@@ -48,13 +48,15 @@ __device__ __forceinline__ void merge_finalize(const MergeArgs& A, size_t idx, f
     }
 }
 
+// One (tile, frame chunk) of the merge: sums the chunk's frames in ascending
+// order into the tile's pixels, then finalises (one chunk) or stores the
+// chunk partial.
 template <int T, int KIND>
-__global__ void __launch_bounds__(256) merge_kernel(MergeArgs A) {
+__device__ __forceinline__ void merge_tile(const MergeArgs& A, int tile, int chunk) {
     using KT = KindTraits<KIND>;
     constexpr int PPT = T * T / 256;
     constexpr int RS = 256 / T;
     constexpr int FB = (PPT >= 16) ? 2 : 4;  // frames loaded ahead per step
-    const int tile = blockIdx.x, chunk = blockIdx.y;
     const int tx0 = (tile % A.tiles_x) * T, ty0 = (tile / A.tiles_x) * T;
     const int lx = threadIdx.x % T, ly0 = threadIdx.x / T;
     const int X = tx0 + lx;
@@ -128,11 +130,16 @@ __global__ void __launch_bounds__(256) merge_kernel(MergeArgs A) {
 }
 
 template <int T, int KIND>
-__global__ void __launch_bounds__(256) merge_finish_kernel(MergeArgs A) {
+__global__ void __launch_bounds__(256) merge_kernel(MergeArgs A) {
+    merge_tile<T, KIND>(A, blockIdx.x, blockIdx.y);
+}
+
+// Second merge pass: chunk partials of one tile added in chunk order.
+template <int T, int KIND>
+__device__ __forceinline__ void merge_finish_tile(const MergeArgs& A, int tile) {
     using KT = KindTraits<KIND>;
     constexpr int PPT = T * T / 256;
     constexpr int RS = 256 / T;
-    const int tile = blockIdx.x;
     const int tx0 = (tile % A.tiles_x) * T, ty0 = (tile / A.tiles_x) * T;
     const int lx = threadIdx.x % T, ly0 = threadIdx.x / T;
     const int X = tx0 + lx;
@@ -153,6 +160,11 @@ __global__ void __launch_bounds__(256) merge_finish_kernel(MergeArgs A) {
         }
         if (X < A.nx && Y < A.ny) merge_finalize<KIND>(A, (size_t)Y * A.nx + X, acc, accu, accd);
     }
+}
+
+template <int T, int KIND>
+__global__ void __launch_bounds__(256) merge_finish_kernel(MergeArgs A) {
+    merge_finish_tile<T, KIND>(A, blockIdx.x);
 }
 
 template <int T, int KIND>
@@ -216,9 +228,20 @@ __global__ void __launch_bounds__(256) set_data_kernel(const float* __restrict__
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// Fixed-order sum of n partials by one 256-thread block: thread t adds the
+// values t, t + 256, ... in eight interleaved running sums (independent loads
+// in flight), which are then combined in a fixed order.
 __device__ float reduce_fixed(const float* __restrict__ partials, int n, float* red) {
-    float s = 0.f;
-    for (int i = threadIdx.x; i < n; i += 256) s += partials[i];
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int i = threadIdx.x;
+    for (; i + 7 * 256 < n; i += 8 * 256) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += partials[i + k * 256];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (i + k * 256 < n) acc[k] += partials[i + k * 256];
+    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     return block_sum256(s, red);
 }
 
@@ -325,6 +348,87 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t s) {
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batched merge and residual reduction over a table of scans
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ void __launch_bounds__(256) batch_merge_kernel(const MergeArgs* __restrict__ D, const int4* __restrict__ items,
+                                                          int n) {
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        merge_tile<T, MK_V>(D[w.x], w.y, w.z);
+    }
+}
+
+template <int T>
+__global__ void __launch_bounds__(256) batch_merge_finish_kernel(const MergeArgs* __restrict__ D,
+                                                                 const int2* __restrict__ items, int n) {
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        merge_finish_tile<T, MK_V>(D[w.x], w.y);
+    }
+}
+
+hipError_t launch_batch_merge(int T, const MergeArgs* D, const int4* items, int n, const int2* fin, int nfin,
+                              int grid, hipStream_t s) {
+    if (n > 0) {
+        const int g = std::min(n, grid);
+        switch (T) {
+            case 16: hipLaunchKernelGGL(batch_merge_kernel<16>, dim3(g), dim3(256), 0, s, D, items, n); break;
+            case 32: hipLaunchKernelGGL(batch_merge_kernel<32>, dim3(g), dim3(256), 0, s, D, items, n); break;
+            case 64: hipLaunchKernelGGL(batch_merge_kernel<64>, dim3(g), dim3(256), 0, s, D, items, n); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (nfin > 0) {
+        const int g = std::min(nfin, grid);
+        switch (T) {
+            case 16: hipLaunchKernelGGL(batch_merge_finish_kernel<16>, dim3(g), dim3(256), 0, s, D, fin, nfin); break;
+            case 32: hipLaunchKernelGGL(batch_merge_finish_kernel<32>, dim3(g), dim3(256), 0, s, D, fin, nfin); break;
+            case 64: hipLaunchKernelGGL(batch_merge_finish_kernel<64>, dim3(g), dim3(256), 0, s, D, fin, nfin); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+// One block per scan: eps_a of the iteration into the scan's history ring,
+// then the gather coefficient of the scan's next iteration becomes beta.
+__global__ void __launch_bounds__(256) batch_eps_kernel(EpsDesc* __restrict__ E, FrameArgs* __restrict__ D,
+                                                        float beta) {
+    __shared__ float red[4];
+    EpsDesc& e = E[blockIdx.x];
+    const float s = reduce_fixed(e.partials, e.n, red);
+    if (threadIdx.x == 0) {
+        const float na2 = e.norm_a2[0];
+        const float v = na2 > 0.f ? sqrtf(s / na2) : 0.f;
+        const int idx = e.hist_idx;
+        e.hist[idx % kHistCap] = v;
+        e.hist_idx = (idx + 1) % kHistCap;
+        if (!isfinite(v)) e.flag[0] = 1;
+        D[blockIdx.x].g = beta;
+    }
+}
+
+__global__ void __launch_bounds__(256) batch_begin_kernel(FrameArgs* __restrict__ D, EpsDesc* __restrict__ E,
+                                                          BatchBegin b, float beta) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= b.n) return;
+    D[s].g = b.g[s];
+    D[s].beta = beta;
+    E[s].hist_idx = b.hist[s];
+}
+
+hipError_t launch_batch_eps(EpsDesc* E, FrameArgs* D, int nscans, float beta, hipStream_t s) {
+    hipLaunchKernelGGL(batch_eps_kernel, dim3(nscans), dim3(256), 0, s, E, D, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_begin(FrameArgs* D, EpsDesc* E, const BatchBegin& b, float beta, hipStream_t s) {
+    hipLaunchKernelGGL(batch_begin_kernel, dim3((b.n + 255) / 256), dim3(256), 0, s, D, E, b, beta);
+    return hipGetLastError();
 }
 
 }  // namespace sharp

@@ -1,0 +1,74 @@
+// Private: the plan object shared by the C ABI implementation files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "../../include/sharp.h"
+#include "sharp_internal.hpp"
+
+namespace sharp {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+inline bool supported_m(int m) { return m == 16 || m == 32 || m == 64 || m == 128 || m == 256; }
+
+// frames per frame-kernel group (must match kernels_frame.hip)
+inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
+
+struct Offsets {
+    size_t tw, pos, tile_ptr, tile_frames, a, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
+    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, total;
+};
+
+}  // namespace sharp
+
+struct sharp_plan_s {
+    int nx = 0, ny = 0, m = 0, K = 0;
+    sharp_options opt{};
+    std::vector<int32_t> pos;
+    int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
+    std::vector<int32_t> tile_ptr, tile_frames;
+    sharp::Offsets off{};
+    size_t resid_cap = 0, gw_slots = 0;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool has_ws = false, has_data = false, has_probe = false, has_object = false;
+    float g = 1.f;
+    long long iter = 0, hist_count = 0;
+    bool gat_stale = false, last_probe_updated = false;
+    // kernel timing (diagnostics): pending (start, stop) event pairs per category
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[sharp::TC_N];
+    std::vector<hipEvent_t> ev_open[sharp::TC_N];
+    sharp::Timer timer{};
+    ~sharp_plan_s() {
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+        for (int c = 0; c < sharp::TC_N; ++c) {
+            for (auto& pr : ev_pairs[c]) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+            for (auto e : ev_open[c]) (void)hipEventDestroy(e);
+        }
+    }
+    const sharp::Timer* tm() const { return timing ? &timer : nullptr; }
+
+    template <class T> T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+    size_t frame_elems() const { return (size_t)K * m * m; }
+    size_t obj_elems() const { return (size_t)nx * ny; }
+};
+
+namespace sharp {
+// argument blocks of a plan's kernels (sharp_api.cpp)
+FrameArgs frame_args(const sharp_plan_s& p);
+MergeArgs merge_args(const sharp_plan_s& p);
+// number of per-block residual partials an iteration's frame launch writes
+int resid_blocks(const sharp_plan_s& p);
+}  // namespace sharp

@@ -12,49 +12,33 @@
 #include <vector>
 
 #include "../../include/sharp.h"
+#include "plan_impl.hpp"
 #include "sharp_internal.hpp"
 
 using namespace sharp;
 
-namespace {
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-bool supported_m(int m) { return m == 16 || m == 32 || m == 64 || m == 128 || m == 256; }
-
-// frames per frame-kernel group (must match kernels_frame.hip)
-int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
-
-struct Offsets {
-    size_t tw, pos, tile_ptr, tile_frames, a, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
-    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, total;
-};
-
-}  // namespace
-
-struct sharp_plan_s {
-    int nx = 0, ny = 0, m = 0, K = 0;
-    sharp_options opt{};
-    std::vector<int32_t> pos;
-    int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
-    std::vector<int32_t> tile_ptr, tile_frames;
-    Offsets off{};
-    size_t resid_cap = 0, gw_slots = 0;
-    char* ws = nullptr;
-    size_t ws_bytes = 0;
-    hipStream_t stream = nullptr;
-    bool has_ws = false, has_data = false, has_probe = false, has_object = false;
-    float g = 1.f;
-    long long iter = 0, hist_count = 0;
-    bool gat_stale = false, last_probe_updated = false;
-
-    template <class T> T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
-    size_t frame_elems() const { return (size_t)K * m * m; }
-    size_t obj_elems() const { return (size_t)nx * ny; }
-};
-
-struct sharp_batch_s;  // defined in sharp_batch.cpp
+static void timer_mark(void* ctx, int cat, int begin) {
+    sharp_plan_s& p = *static_cast<sharp_plan_s*>(ctx);
+    hipEvent_t e = nullptr;
+    if (!p.ev_pool.empty()) {
+        e = p.ev_pool.back();
+        p.ev_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return;
+    }
+    if (hipEventRecord(e, p.stream) != hipSuccess) {
+        p.ev_pool.push_back(e);
+        return;
+    }
+    if (begin) {
+        p.ev_open[cat].push_back(e);
+    } else if (!p.ev_open[cat].empty()) {
+        p.ev_pairs[cat].emplace_back(p.ev_open[cat].back(), e);
+        p.ev_open[cat].pop_back();
+    } else {
+        p.ev_pool.push_back(e);
+    }
+}
 
 extern "C" const char* sharp_status_string(int s) {
     switch (s) {
@@ -263,7 +247,7 @@ extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
 // ---------------------------------------------------------------------------
 // argument blocks
 // ---------------------------------------------------------------------------
-static FrameArgs frame_args(const sharp_plan_s& p) {
+FrameArgs sharp::frame_args(const sharp_plan_s& p) {
     FrameArgs A{};
     A.K = p.K;
     A.M = p.m;
@@ -286,7 +270,7 @@ static FrameArgs frame_args(const sharp_plan_s& p) {
     return A;
 }
 
-static MergeArgs merge_args(const sharp_plan_s& p) {
+MergeArgs sharp::merge_args(const sharp_plan_s& p) {
     MergeArgs A{};
     A.M = p.m;
     A.nx = p.nx;
@@ -311,6 +295,10 @@ static MergeArgs merge_args(const sharp_plan_s& p) {
     A.g = p.g;
     A.eps_D = p.opt.eps_D;
     return A;
+}
+
+int sharp::resid_blocks(const sharp_plan_s& p) {
+    return p.m == 256 ? p.K * 16 : (p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
 }
 
 static int density(sharp_plan_s& p) {
@@ -392,18 +380,24 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     FrameArgs A = frame_args(p);
     A.beta = beta;
     int blocks = 0;
-    HIPCHK(launch_frame(FM_RAAR, A, 0, s, &blocks));
+    const Timer* t = p.tm();
+    HIPCHK(launch_frame(FM_RAAR, A, 0, s, &blocks, t));
     if (p.gat_stale) {
         HIPCHK(launch_copy(p.ws + p.off.w_gat, p.ws + p.off.w_cur, (size_t)p.m * p.m * sizeof(float2), s));
         p.gat_stale = false;
     }
+    if (t) t->begin(TC_REDUCE);
     HIPCHK(launch_eps(p.at<float>(p.off.resid), blocks, p.at<float>(p.off.scal), p.at<float>(p.off.hist),
                       (int)(p.hist_count % kHistCap), p.at<int>(p.off.flag), s));
+    if (t) t->end(TC_REDUCE);
     p.hist_count++;
     p.g = beta;
     MergeArgs Mg = merge_args(p);
+    if (t) t->begin(TC_MERGE);
     HIPCHK(launch_merge(probe_due ? MK_VU : MK_V, Mg, p.ntiles, s));
+    if (t) t->end(TC_MERGE);
     if (probe_due) {
+        if (t) t->begin(TC_PROBE);
         HIPCHK(launch_probe_partial(p.m, p.K, p.at<int>(p.off.pos), p.nx, p.ny, p.opt.periodic, p.at<float2>(p.off.u),
                                     p.at<float2>(p.off.w_cur), p.at<float2>(p.off.psi_v), p.at<float2>(p.off.psi_l),
                                     beta, p.probe_chunks, p.at<float2>(p.off.pnum), p.at<float>(p.off.pden), s));
@@ -411,6 +405,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
                                    p.at<float2>(p.off.w_gat), p.at<float2>(p.off.w_cur), s));
         int st = density(p);
         if (st) return st;
+        if (t) t->end(TC_PROBE);
         p.gat_stale = true;
     }
     p.last_probe_updated = probe_due;
@@ -492,12 +487,14 @@ extern "C" int sharp_grad(sharp_plan p, const void* d_psi, const void* d_w, floa
     A.w = (const float2*)d_w;
     A.w_g = (const float2*)d_w;
     int blocks = 0;
-    HIPCHK(launch_frame(FM_GRAD, A, p->grad_groups, s, &blocks));
+    HIPCHK(launch_frame(FM_GRAD, A, p->grad_groups, s, &blocks, p->tm()));
     HIPCHK(launch_loss(p->at<float>(p->off.resid), p->m == 256 ? p->K * 16 : blocks, d_loss, p->at<int>(p->off.flag), s));
     if (d_gpsi) {
         MergeArgs Mg = merge_args(*p);
         Mg.out = (float2*)d_gpsi;
+        if (p->timing) p->timer.begin(TC_MERGE);
         HIPCHK(launch_merge(MK_RAW, Mg, p->ntiles, s));
+        if (p->timing) p->timer.end(TC_MERGE);
     }
     if (d_gw) {
         const int slots = frame_partial_slots(p->m, FM_GRAD, blocks);
@@ -668,5 +665,35 @@ extern "C" int sharp_get_plan_csr(sharp_plan p, int32_t* h_ptr, int32_t* h_frame
     if (!p || !h_ptr || !h_frames) return SHARP_ERR_INVALID_ARG;
     std::memcpy(h_ptr, p->tile_ptr.data(), p->tile_ptr.size() * sizeof(int32_t));
     std::memcpy(h_frames, p->tile_frames.data(), p->tile_frames.size() * sizeof(int32_t));
+    return SHARP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+extern "C" int sharp_timing_enable(sharp_plan p, int on) {
+    if (!p) return SHARP_ERR_INVALID_ARG;
+    p->timing = on != 0;
+    p->timer.ctx = p;
+    p->timer.mark = timer_mark;
+    return SHARP_OK;
+}
+
+extern "C" int sharp_timing_read(sharp_plan p, double* h_ms, long long* h_launches) {
+    if (!p || !h_ms || !h_launches) return SHARP_ERR_INVALID_ARG;
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (int c = 0; c < TC_N; ++c) {
+        h_ms[c] = 0.0;
+        h_launches[c] = 0;
+        for (auto& pr : p->ev_pairs[c]) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            h_ms[c] += ms;
+            h_launches[c] += 1;
+            p->ev_pool.push_back(pr.first);
+            p->ev_pool.push_back(pr.second);
+        }
+        p->ev_pairs[c].clear();
+    }
     return SHARP_OK;
 }

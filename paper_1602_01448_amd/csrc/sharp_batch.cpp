@@ -1,14 +1,256 @@
-// Batched execution of independent plans (placeholder until the batched launch lands).
+// Batched RAAR over independent scans (plans) of uneven sizes.
+//
+// One iteration of every scan is one fixed launch sequence regardless of the
+// number of scans: per frame-size class a persistent frame kernel striding
+// over a (scan, item) work list, one residual reduction with a block per
+// scan, and per merge-tile class a persistent merge kernel over (scan, tile,
+// chunk) items.  n iterations are captured once into a hipGraph (keyed by n
+// and beta) and replayed on the batch's own stream, which is ordered after
+// the caller's stream with events.  Work items run exactly the single-scan
+// arithmetic, so each scan's result equals its single-scan run bit for bit.
 #include <hip/hip_runtime.h>
 
-#include "../../include/sharp.h"
+#include <algorithm>
+#include <map>
+#include <new>
+#include <utility>
+#include <vector>
 
-extern "C" int sharp_batch_create(sharp_batch* out, int, const sharp_plan*) {
-    if (out) *out = nullptr;
-    return SHARP_ERR_INVALID_ARG;
+#include "../../include/sharp.h"
+#include "plan_impl.hpp"
+#include "sharp_internal.hpp"
+
+using namespace sharp;
+
+namespace {
+constexpr int kM[5] = {16, 32, 64, 128, 256};
+constexpr int kT[3] = {16, 32, 64};
+int m_class(int m) {
+    for (int i = 0; i < 5; ++i)
+        if (kM[i] == m) return i;
+    return -1;
 }
-extern "C" void sharp_batch_destroy(sharp_batch) {}
-extern "C" size_t sharp_batch_workspace_bytes(sharp_batch) { return 0; }
-extern "C" int sharp_batch_set_workspace(sharp_batch, void*, size_t) { return SHARP_ERR_INVALID_ARG; }
-extern "C" int sharp_batch_set_stream(sharp_batch, void*) { return SHARP_ERR_INVALID_ARG; }
-extern "C" int sharp_batch_raar_iterate(sharp_batch, int, float) { return SHARP_ERR_INVALID_ARG; }
+int t_class(int t) {
+    for (int i = 0; i < 3; ++i)
+        if (kT[i] == t) return i;
+    return -1;
+}
+}  // namespace
+
+struct sharp_batch_s {
+    std::vector<sharp_plan_s*> plans;
+    std::vector<int2> frame_items[5];     // per frame-size class
+    std::vector<int4> merge_items[3];     // per merge-tile class
+    std::vector<int2> finish_items[3];
+    struct {
+        size_t fargs, margs, eps, fitems[5], mitems[3], fin[3], total;
+    } off{};
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t user = nullptr;      // caller's stream
+    hipStream_t own = nullptr;       // batch stream (graphs are captured and replayed here)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int grid_frame[5][3] = {};
+    int grid_merge = 0;
+    std::map<std::pair<int, float>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+
+    ~sharp_batch_s() {
+        for (auto& kv : graphs) {
+            (void)hipGraphExecDestroy(kv.second.second);
+            (void)hipGraphDestroy(kv.second.first);
+        }
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (own) (void)hipStreamDestroy(own);
+    }
+    template <class T> T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+};
+
+extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan* plans) {
+    if (!out) return SHARP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!plans || nplans < 1 || nplans > kMaxBatch) return SHARP_ERR_INVALID_ARG;
+    for (int i = 0; i < nplans; ++i) {
+        sharp_plan_s* p = plans[i];
+        if (!p) return SHARP_ERR_INVALID_ARG;
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == p) return SHARP_ERR_INVALID_ARG;
+        if (p->opt.probe_every != 0) return SHARP_ERR_INVALID_ARG;
+        if (!p->has_ws || !p->has_data || !p->has_probe || !p->has_object) return SHARP_ERR_NOT_READY;
+    }
+    sharp_batch_s* b = new (std::nothrow) sharp_batch_s();
+    if (!b) return SHARP_ERR_HOST_ALLOC;
+    try {
+        for (int s = 0; s < nplans; ++s) {
+            sharp_plan_s* p = plans[s];
+            b->plans.push_back(p);
+            const int mc = m_class(p->m);
+            const int items = resid_blocks(*p);  // frame groups (m <= 128) or frame row blocks (m = 256)
+            for (int it = 0; it < items; ++it) b->frame_items[mc].push_back(make_int2(s, it));
+            const int tc = t_class(p->T);
+            for (int t = 0; t < p->ntiles; ++t)
+                for (int c = 0; c < p->split; ++c) b->merge_items[tc].push_back(make_int4(s, t, c, 0));
+            if (p->split > 1)
+                for (int t = 0; t < p->ntiles; ++t) b->finish_items[tc].push_back(make_int2(s, t));
+        }
+        size_t cur = 0;
+        auto take = [&](size_t bytes) {
+            size_t at = cur;
+            cur = align_up(cur + bytes);
+            return at;
+        };
+        b->off.fargs = take(nplans * sizeof(FrameArgs));
+        b->off.margs = take(nplans * sizeof(MergeArgs));
+        b->off.eps = take(nplans * sizeof(EpsDesc));
+        for (int c = 0; c < 5; ++c) b->off.fitems[c] = take(b->frame_items[c].size() * sizeof(int2));
+        for (int c = 0; c < 3; ++c) {
+            b->off.mitems[c] = take(b->merge_items[c].size() * sizeof(int4));
+            b->off.fin[c] = take(b->finish_items[c].size() * sizeof(int2));
+        }
+        b->off.total = cur;
+    } catch (...) {
+        delete b;
+        return SHARP_ERR_HOST_ALLOC;
+    }
+    *out = b;
+    return SHARP_OK;
+}
+
+extern "C" void sharp_batch_destroy(sharp_batch b) { delete b; }
+
+extern "C" size_t sharp_batch_workspace_bytes(sharp_batch b) { return b ? b->off.total : 0; }
+
+extern "C" int sharp_batch_set_stream(sharp_batch b, void* stream) {
+    if (!b) return SHARP_ERR_INVALID_ARG;
+    b->user = (hipStream_t)stream;
+    return SHARP_OK;
+}
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return SHARP_ERR_HIP; \
+    } while (0)
+
+extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
+    if (!b || !d || ((uintptr_t)d % kAlign) != 0) return SHARP_ERR_INVALID_ARG;
+    if (bytes < b->off.total) return SHARP_ERR_WORKSPACE_TOO_SMALL;
+    b->ws = (char*)d;
+    b->ws_bytes = bytes;
+    for (auto& kv : b->graphs) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    b->graphs.clear();
+    if (!b->own) HIPCHK(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking));
+    if (!b->ev_in) HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    if (!b->ev_out) HIPCHK(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    const int n = (int)b->plans.size();
+    std::vector<FrameArgs> fa(n);
+    std::vector<MergeArgs> ma(n);
+    std::vector<EpsDesc> ea(n);
+    for (int s = 0; s < n; ++s) {
+        sharp_plan_s& p = *b->plans[s];
+        fa[s] = frame_args(p);
+        ma[s] = merge_args(p);
+        ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks(p), 0, p.at<float>(p.off.scal),
+                        p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
+    }
+    hipStream_t st = b->own;
+    HIPCHK(hipMemcpyAsync(b->ws + b->off.fargs, fa.data(), n * sizeof(FrameArgs), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->ws + b->off.margs, ma.data(), n * sizeof(MergeArgs), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->ws + b->off.eps, ea.data(), n * sizeof(EpsDesc), hipMemcpyHostToDevice, st));
+    for (int c = 0; c < 5; ++c)
+        if (!b->frame_items[c].empty())
+            HIPCHK(hipMemcpyAsync(b->ws + b->off.fitems[c], b->frame_items[c].data(),
+                                  b->frame_items[c].size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    for (int c = 0; c < 3; ++c) {
+        if (!b->merge_items[c].empty())
+            HIPCHK(hipMemcpyAsync(b->ws + b->off.mitems[c], b->merge_items[c].data(),
+                                  b->merge_items[c].size() * sizeof(int4), hipMemcpyHostToDevice, st));
+        if (!b->finish_items[c].empty())
+            HIPCHK(hipMemcpyAsync(b->ws + b->off.fin[c], b->finish_items[c].data(),
+                                  b->finish_items[c].size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    // persistent grids: resident blocks per CU x CUs
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int c = 0; c < 5; ++c)
+        for (int ph = 0; ph < (kM[c] == 256 ? 3 : 1); ++ph) {
+            int per = 1;
+            HIPCHK(batch_frame_prepare(kM[c], ph, &per));
+            b->grid_frame[c][ph] = std::max(1, per * cus);
+        }
+    b->grid_merge = 8 * cus;
+    return SHARP_OK;
+}
+
+static int enqueue_iterations(sharp_batch_s& b, int n, float beta, hipStream_t s) {
+    FrameArgs* D = b.at<FrameArgs>(b.off.fargs);
+    const MergeArgs* DM = b.at<MergeArgs>(b.off.margs);
+    EpsDesc* E = b.at<EpsDesc>(b.off.eps);
+    const int ns = (int)b.plans.size();
+    for (int l = 0; l < n; ++l) {
+        for (int c = 0; c < 5; ++c) {
+            const int cnt = (int)b.frame_items[c].size();
+            if (!cnt) continue;
+            const int2* items = b.at<int2>(b.off.fitems[c]);
+            for (int ph = 0; ph < (kM[c] == 256 ? 3 : 1); ++ph)
+                HIPCHK(launch_batch_frame(kM[c], ph, D, items, cnt, std::min(cnt, b.grid_frame[c][ph]), s));
+        }
+        HIPCHK(launch_batch_eps(E, D, ns, beta, s));
+        for (int c = 0; c < 3; ++c)
+            HIPCHK(launch_batch_merge(kT[c], DM, b.at<int4>(b.off.mitems[c]), (int)b.merge_items[c].size(),
+                                      b.at<int2>(b.off.fin[c]), (int)b.finish_items[c].size(), b.grid_merge, s));
+    }
+    return SHARP_OK;
+}
+
+extern "C" int sharp_batch_raar_iterate(sharp_batch b, int n, float beta) {
+    if (!b || n < 0 || !(beta > 0.f && beta <= 1.f)) return SHARP_ERR_INVALID_ARG;
+    if (!b->ws) return SHARP_ERR_NOT_READY;
+    for (sharp_plan_s* p : b->plans)
+        if (!p->has_ws || !p->has_data || !p->has_probe || !p->has_object || p->gat_stale)
+            return SHARP_ERR_NOT_READY;
+    if (n == 0) return SHARP_OK;
+    BatchBegin bb{};
+    bb.n = (int)b->plans.size();
+    for (int s = 0; s < bb.n; ++s) {
+        bb.g[s] = b->plans[s]->g;
+        bb.hist[s] = (int)(b->plans[s]->hist_count % kHistCap);
+    }
+    // order the batch stream after the caller's stream
+    HIPCHK(hipEventRecord(b->ev_in, b->user));
+    HIPCHK(hipStreamWaitEvent(b->own, b->ev_in, 0));
+    HIPCHK(launch_batch_begin(b->at<FrameArgs>(b->off.fargs), b->at<EpsDesc>(b->off.eps), bb, beta, b->own));
+    const auto key = std::make_pair(n, beta);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        HIPCHK(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+        int st = enqueue_iterations(*b, n, beta, b->own);
+        hipError_t ec = hipStreamEndCapture(b->own, &g);
+        if (st != SHARP_OK || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != SHARP_OK ? st : SHARP_ERR_HIP;
+        }
+        if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return SHARP_ERR_HIP;
+        }
+        it = b->graphs.emplace(key, std::make_pair(g, ge)).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second.second, b->own));
+    HIPCHK(hipEventRecord(b->ev_out, b->own));
+    HIPCHK(hipStreamWaitEvent(b->user, b->ev_out, 0));
+    for (sharp_plan_s* p : b->plans) {
+        p->iter += n;
+        p->hist_count += n;
+        p->g = beta;
+        p->last_probe_updated = false;
+    }
+    return SHARP_OK;
+}

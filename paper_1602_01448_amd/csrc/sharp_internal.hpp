@@ -69,8 +69,19 @@ struct MergeArgs {
     float g, eps_D;
 };
 
+// Optional per-launch timing hook (HIP events recorded on the launch stream).
+enum TimerCat : int { TC_FRAME = 0, TC_COLS = 1, TC_FRAME_OUT = 2, TC_MERGE = 3, TC_REDUCE = 4, TC_PROBE = 5,
+                      TC_COPY = 6, TC_N = 8 };
+struct Timer {
+    void* ctx = nullptr;
+    void (*mark)(void* ctx, int cat, int begin) = nullptr;
+    void begin(int c) const { if (mark) mark(ctx, c, 1); }
+    void end(int c) const { if (mark) mark(ctx, c, 0); }
+};
+
 // launchers (kernels_frame.hip)
-hipError_t launch_frame(int mode, const FrameArgs& a, int grid_hint, hipStream_t s, int* blocks_used);
+hipError_t launch_frame(int mode, const FrameArgs& a, int grid_hint, hipStream_t s, int* blocks_used,
+                        const Timer* t = nullptr);
 int frame_partial_slots(int M, int mode, int blocks);  // gw partial slots per launch
 hipError_t launch_probe_partial(int M, int K, const int* pos, int nx, int ny, int periodic,
                                 const float2* u, const float2* w, const float2* psi_v,
@@ -92,5 +103,28 @@ hipError_t launch_mean_amp(const float* a, int K, int M, float2* out, hipStream_
 hipError_t launch_roll_probe(const float2* src, int M, float2* w_cur, float2* w_gat, hipStream_t s);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// batched execution (kernels_frame.hip, kernels_merge.hip)
+constexpr int kMaxBatch = 256;
+struct EpsDesc {
+    const float* partials;
+    int n;
+    int hist_idx;
+    const float* norm_a2;
+    float* hist;
+    int* flag;
+};
+struct BatchBegin {
+    int n;
+    float g[kMaxBatch];
+    int hist[kMaxBatch];
+};
+hipError_t batch_frame_prepare(int M, int phase, int* blocks_per_cu);
+hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* items, int n, int grid,
+                              hipStream_t s);
+hipError_t launch_batch_merge(int T, const MergeArgs* D, const int4* items, int n, const int2* fin, int nfin,
+                              int grid, hipStream_t s);
+hipError_t launch_batch_eps(EpsDesc* E, FrameArgs* D, int nscans, float beta, hipStream_t s);
+hipError_t launch_batch_begin(FrameArgs* D, EpsDesc* E, const BatchBegin& b, float beta, hipStream_t s);
 
 }  // namespace sharp

@@ -165,6 +165,21 @@ class Plan:
         check(lib.sharp_apply(self._h, OPS[op], _ptr(x), _ptr(out)), f"sharp_apply({op})")
         return out
 
+    # -- kernel timing -------------------------------------------------------
+    TIMER_NAMES = ("frame", "cols", "frame_out", "merge", "reduce", "probe", "copy", "spare")
+
+    def timing(self, on: bool = True):
+        check(lib.sharp_timing_enable(self._h, int(on)), "sharp_timing_enable")
+        return self
+
+    def timing_read(self) -> dict:
+        import ctypes
+        ms = (ctypes.c_double * 8)()
+        n = (ctypes.c_longlong * 8)()
+        self._stream()
+        check(lib.sharp_timing_read(self._h, ms, n), "sharp_timing_read")
+        return {name: (ms[i], n[i]) for i, name in enumerate(self.TIMER_NAMES) if n[i]}
+
     # -- checkpoint ----------------------------------------------------------
     def state(self) -> torch.Tensor:
         buf = torch.empty(lib.sharp_state_bytes(self._h), dtype=torch.uint8, device=self.device)
