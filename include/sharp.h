@@ -50,7 +50,8 @@ enum sharp_status {
     SHARP_ERR_WORKSPACE_TOO_SMALL = -5,
     SHARP_ERR_NONFINITE = -6,             /* NaN/Inf seen in data or in an iterate */
     SHARP_ERR_HIP = -7,                   /* a HIP runtime call failed */
-    SHARP_ERR_HOST_ALLOC = -8             /* host metadata allocation failed */
+    SHARP_ERR_HOST_ALLOC = -8,            /* host metadata allocation failed */
+    SHARP_ERR_DEVICE_WAIT = -9            /* a bounded device-side wait expired (work left undone) */
 };
 
 /* Static text for a status code (never NULL). */
@@ -69,7 +70,12 @@ typedef struct sharp_options {
     int tile;         /* merge tile side in object pixels: 16, 32 or 64 (0 = tuned) */
     int merge_split;  /* frame chunks per tile in the first merge pass, >= 1 (0 = tuned) */
     int grad_groups;  /* workgroups of the gradient frame kernel (0 = tuned) */
-    int reserved[5];  /* must be zero */
+    int frame_launch; /* m = 256 RAAR frame phase: 0 = tuned, 1 = three launches (row,
+                         column, row passes), 2 = one persistent launch per iteration in
+                         which each XCD streams its own frames through its L2 */
+    int fft_block;    /* m = 256, three-launch form: threads per pass workgroup, 128, 256 or
+                         512 (8, 16 or 32 rows / columns per workgroup); 0 = tuned */
+    int reserved[3];  /* must be zero */
 } sharp_options;
 
 /* ------------------------------------------------------------------------
@@ -196,7 +202,7 @@ int sharp_set_state(sharp_plan plan, const void* d_state);
  * ---------------------------------------------------------------------- */
 typedef struct sharp_plan_info {
     int nx, ny, m, K, periodic;
-    int tile, tiles_x, tiles_y, merge_split, grad_groups;
+    int tile, tiles_x, tiles_y, merge_split, grad_groups, frame_launch, fft_block;
     long long csr_nnz;        /* (tile, frame) incidences */
     long long iteration;      /* iterations run since sharp_set_object */
 } sharp_plan_info;

@@ -19,7 +19,7 @@ STATUS = {
     0: "SHARP_OK", -1: "SHARP_ERR_INVALID_ARG", -2: "SHARP_ERR_UNSUPPORTED_SIZE",
     -3: "SHARP_ERR_POSITION_OUT_OF_RANGE", -4: "SHARP_ERR_NOT_READY",
     -5: "SHARP_ERR_WORKSPACE_TOO_SMALL", -6: "SHARP_ERR_NONFINITE", -7: "SHARP_ERR_HIP",
-    -8: "SHARP_ERR_HOST_ALLOC",
+    -8: "SHARP_ERR_HOST_ALLOC", -9: "SHARP_ERR_DEVICE_WAIT",
 }
 OPS = {"F": 0, "FINV": 1, "Q": 2, "QSTAR": 3, "PA": 4, "PQ": 5, "OBJECT": 6}
 
@@ -34,13 +34,15 @@ class SharpError(RuntimeError):
 
 class SharpOptions(Structure):
     _fields_ = [("periodic", c_int), ("probe_every", c_int), ("probe_start", c_int), ("eps_D", c_float),
-                ("tile", c_int), ("merge_split", c_int), ("grad_groups", c_int), ("reserved", c_int * 5)]
+                ("tile", c_int), ("merge_split", c_int), ("grad_groups", c_int), ("frame_launch", c_int),
+                ("fft_block", c_int), ("reserved", c_int * 3)]
 
 
 class SharpPlanInfo(Structure):
     _fields_ = [("nx", c_int), ("ny", c_int), ("m", c_int), ("K", c_int), ("periodic", c_int),
                 ("tile", c_int), ("tiles_x", c_int), ("tiles_y", c_int), ("merge_split", c_int),
-                ("grad_groups", c_int), ("csr_nnz", c_longlong), ("iteration", c_longlong)]
+                ("grad_groups", c_int), ("frame_launch", c_int), ("fft_block", c_int), ("csr_nnz", c_longlong),
+                ("iteration", c_longlong)]
 
 
 # (name, restype, argtypes) for every symbol declared in include/sharp.h

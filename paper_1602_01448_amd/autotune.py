@@ -1,0 +1,211 @@
+"""Autotuner for the launch shapes of a scan geometry.
+
+Times candidate launch configurations of the library on the GPU and keeps the
+fastest per geometry:
+
+* merge tile side (16, 32, 64) and frame-chunk split of the overlap merge;
+* for 256 x 256 frames, the frame-phase form (three launches, or one
+  persistent XCD-local launch) and the pass workgroup size (128, 256 or 512
+  threads, i.e. 8, 16 or 32 rows / columns of a frame per workgroup);
+* the workgroup count of the gradient frame kernel.
+
+Candidates are timed with HIP events over a few RAAR iterations (or gradient
+calls) on synthetic data of the geometry's shape; every candidate computes
+the same iterates (the tests check this), so only time decides.  Results go
+to a JSON cache keyed by GPU architecture and geometry; ``Plan.tuned`` and
+the benchmark read it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from .plan import Plan
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "gfx950.json")
+
+
+def _arch() -> str:
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "gfx950"
+
+
+def geometry_key(kind: str, nx: int, ny: int, m: int, positions, periodic: bool) -> str:
+    pos = np.ascontiguousarray(positions, dtype=np.int32)
+    digest = hashlib.sha1(pos.tobytes()).hexdigest()[:12]
+    return f"{_arch()}:{kind}:{nx}x{ny}:m{m}:K{len(pos)}:p{int(periodic)}:{digest}"
+
+
+def load_cache(path: str = CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: dict, path: str = CACHE) -> None:
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(kind: str, nx: int, ny: int, m: int, positions, periodic: bool = False, path: str = CACHE) -> dict:
+    return load_cache(path).get(geometry_key(kind, nx, ny, m, positions, periodic), {}).get("options", {})
+
+
+def _merge_candidates(n: int):
+    out = []
+    for tile in (16, 32, 64):
+        tiles = ((n + tile - 1) // tile) ** 2
+        splits = {1}
+        s = 1
+        while tiles * s < 2048 and s < 16:
+            s *= 2
+            splits.add(s)
+        out += [{"tile": tile, "merge_split": sp} for sp in sorted(splits)]
+    return out
+
+
+def _frame_candidates(m: int):
+    if m != 256:
+        return [{}]
+    return [{"frame_launch": 1, "fft_block": b} for b in (128, 256, 512)] + [{"frame_launch": 2}]
+
+
+def _synthetic(plan: Plan, seed: int):
+    g = torch.Generator(device=plan.device)
+    g.manual_seed(seed)
+    dev = plan.device
+    obj = torch.polar(0.5 + 0.5 * torch.rand(plan.ny, plan.nx, generator=g, device=dev),
+                      torch.rand(plan.ny, plan.nx, generator=g, device=dev) * 3.0 - 1.5)
+    yy = torch.arange(plan.m, device=dev, dtype=torch.float32) - plan.m // 2
+    probe = torch.exp(-(yy[:, None] ** 2 + yy[None, :] ** 2) / (2 * (plan.m / 5.0) ** 2)).to(torch.complex64)
+    return obj.to(torch.complex64).contiguous(), probe.contiguous()
+
+
+def _time_raar(plan: Plan, iters: int, reps: int) -> float:
+    obj, probe = _synthetic(plan, 1602)
+    I = plan.simulate(obj, probe)
+    plan.set_data(I).set_probe(probe).set_object(torch.ones_like(obj))
+    plan.raar(1, 0.75)
+    best = float("inf")
+    for _ in range(reps):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(plan.device)
+        t0.record()
+        plan.raar(iters, 0.75)
+        t1.record()
+        torch.cuda.synchronize(plan.device)
+        best = min(best, t0.elapsed_time(t1) / iters)
+    plan.sync()
+    return best
+
+
+def _time_grad(plan: Plan, reps: int) -> float:
+    obj, probe = _synthetic(plan, 1603)
+    plan.set_data(plan.simulate(obj, probe))
+    psi = torch.ones_like(obj)
+    plan.grad(psi, probe)
+    best = float("inf")
+    for _ in range(reps):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(plan.device)
+        t0.record()
+        plan.grad(psi, probe)
+        t1.record()
+        torch.cuda.synchronize(plan.device)
+        best = min(best, t0.elapsed_time(t1))
+    return best
+
+
+def tune_raar(nx: int, ny: int, m: int, positions, periodic: bool = False, iters: int = 3, reps: int = 3,
+              path: str = CACHE, verbose: bool = False) -> dict:
+    """Fastest (merge, frame-phase) options for RAAR on this geometry; cached."""
+    key = geometry_key("raar", nx, ny, m, positions, periodic)
+    results = []
+    best_merge, best_t = {}, float("inf")
+    for mc in _merge_candidates(max(nx, ny)):        # merge options with the default frame phase
+        p = Plan(nx, ny, m, positions, periodic=periodic, **mc)
+        t = _time_raar(p, iters, reps)
+        results.append((mc, t))
+        if verbose:
+            print(f"  {mc}: {t:.4f} ms/iteration", flush=True)
+        if t < best_t:
+            best_merge, best_t = mc, t
+        del p
+    best = dict(best_merge)
+    for fc in _frame_candidates(m)[1:] if m == 256 else []:
+        opts = {**best_merge, **fc}
+        p = Plan(nx, ny, m, positions, periodic=periodic, **opts)
+        t = _time_raar(p, iters, reps)
+        results.append((opts, t))
+        if verbose:
+            print(f"  {opts}: {t:.4f} ms/iteration", flush=True)
+        if t < best_t:
+            best, best_t = opts, t
+        del p
+    cache = load_cache(path)
+    cache[key] = {"options": best, "ms_per_iteration": round(best_t, 5), "tried": len(results),
+                  "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    save_cache(cache, path)
+    return best
+
+
+def tune_grad(nx: int, ny: int, m: int, positions, periodic: bool = False, reps: int = 5, path: str = CACHE,
+              verbose: bool = False) -> dict:
+    """Fastest gradient grid (and merge tile) on this geometry; cached."""
+    key = geometry_key("grad", nx, ny, m, positions, periodic)
+    best, best_t = {}, float("inf")
+    for gg in (64, 128, 256, 512, 1024):
+        for tile in (16, 32, 64):
+            opts = {"grad_groups": gg, "tile": tile}
+            p = Plan(nx, ny, m, positions, periodic=periodic, **opts)
+            t = _time_grad(p, reps)
+            if verbose:
+                print(f"  {opts}: {t:.4f} ms/call", flush=True)
+            if t < best_t:
+                best, best_t = opts, t
+            del p
+    cache = load_cache(path)
+    cache[key] = {"options": best, "ms_per_call": round(best_t, 5), "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    save_cache(cache, path)
+    return best
+
+
+def main() -> None:
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from sharp_data import gen
+
+    ap = argparse.ArgumentParser(description="tune launch shapes of the benchmark workloads")
+    ap.add_argument("--workloads", default="1,2,3,4,batch")
+    ap.add_argument("--path", default=CACHE)
+    args = ap.parse_args()
+    for w in args.workloads.split(","):
+        if w == "batch":
+            for s in gen.batch_scans():
+                print(f"tuning raar {s.name}", flush=True)
+                tune_raar(s.n, s.n, s.m, s.positions, path=args.path, reps=2, iters=2)
+            continue
+        s = gen.config_scan(int(w))
+        if int(w) == 4:
+            print(f"tuning grad {s.name}", flush=True)
+            print(tune_grad(s.n, s.n, s.m, s.positions, path=args.path, verbose=True), flush=True)
+        else:
+            print(f"tuning raar {s.name}", flush=True)
+            print(tune_raar(s.n, s.n, s.m, s.positions, path=args.path, verbose=True), flush=True)
+
+
+if __name__ == "__main__":
+    main()

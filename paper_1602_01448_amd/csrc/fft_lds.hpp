@@ -152,10 +152,15 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ lds, const float2
     constexpr int BPL = N / R;
     static_assert(NB % NT == 0, "butterflies must divide evenly over threads");
     constexpr int PER = NB / NT;
+    // An opaque copy of the thread index: keeps the compiler from hoisting
+    // every stage's address arithmetic out of the caller's loops (which
+    // would hold hundreds of addresses live in registers).
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     float2 v[PER][R];
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-        const int b = threadIdx.x + p * NT;
+        const int b = tid + p * NT;
         const int base = Lay::base(b), j = Lay::j(b);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[p][r] = lds[pidx(base + (j + r * BPL) * Lay::stride)];
@@ -163,7 +168,7 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ lds, const float2
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-        const int b = threadIdx.x + p * NT;
+        const int b = tid + p * NT;
         const int base = Lay::base(b), j = Lay::j(b);
         const int k = j % L;
         if constexpr (L > 1) {

@@ -16,6 +16,8 @@
 //    a row pass (gather + row FFTs), a column pass (column FFTs + modulus +
 //    inverse column FFTs) and a row pass (inverse row FFTs + epilogue), with
 //    the row-transformed frames kept in an HBM stage buffer between passes.
+#include <algorithm>
+
 #include "fft_lds.hpp"
 #include "sharp_internal.hpp"
 
@@ -69,15 +71,36 @@ __device__ __forceinline__ void fft_1d(float2* lds, const float2* twl, Post& pos
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrap(int v, int n) { return v >= n ? v - n : v; }
 
-__device__ __forceinline__ float2 ldc(const float2* p, size_t i) { return p[i]; }
+// Thread index the compiler cannot treat as loop-invariant: per-item address
+// arithmetic stays inside the item instead of being hoisted (and held live)
+// across the item loop.
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
 
-__device__ __forceinline__ void ld2(const float2* __restrict__ p, size_t i, float2& a, float2& b) {
-    float4 t = *reinterpret_cast<const float4*>(p + i);
+// Memory access through a uniform base pointer plus a 32-bit element offset
+// (the compiler then addresses with a scalar base and one vector offset).
+__device__ __forceinline__ const char* byte_at(const void* p, unsigned elem, unsigned size) {
+    return reinterpret_cast<const char*>(p) + elem * size;
+}
+__device__ __forceinline__ void ld2(const float2* __restrict__ p, unsigned i, float2& a, float2& b) {
+    const float4 t = *reinterpret_cast<const float4*>(byte_at(p, i, 8u));
     a = make_float2(t.x, t.y);
     b = make_float2(t.z, t.w);
 }
-__device__ __forceinline__ void st2(float2* __restrict__ p, size_t i, float2 a, float2 b) {
-    *reinterpret_cast<float4*>(p + i) = make_float4(a.x, a.y, b.x, b.y);
+__device__ __forceinline__ void st2(float2* __restrict__ p, unsigned i, float2 a, float2 b) {
+    *reinterpret_cast<float4*>(const_cast<char*>(byte_at(p, i, 8u))) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ float2 ldf2(const float* __restrict__ p, unsigned i) {
+    return *reinterpret_cast<const float2*>(byte_at(p, i, 4u));
+}
+__device__ __forceinline__ void stf2(float* __restrict__ p, unsigned i, float a, float b) {
+    *reinterpret_cast<float2*>(const_cast<char*>(byte_at(p, i, 4u))) = make_float2(a, b);
+}
+__device__ __forceinline__ float2 ldc(const float2* __restrict__ p, unsigned i) {
+    return *reinterpret_cast<const float2*>(byte_at(p, i, 8u));
 }
 
 // Gather of two horizontally adjacent object pixels for frame pixel (y, x), (y, x+1).
@@ -89,24 +112,26 @@ __device__ __forceinline__ void gather2(const FrameArgs& A, int frame, int y, in
         gx = wrap(gx, A.nx);
         gx1 = wrap(gx1, A.nx);
     }
-    const float2* row = A.psi + (size_t)gy * A.nx;
-    p0 = row[gx];
-    p1 = row[gx1];
+    const unsigned row = (unsigned)gy * (unsigned)A.nx;
+    p0 = ldc(A.psi, row + gx);
+    p1 = ldc(A.psi, row + gx1);
 }
 
 // Prologue: the frame values z entering the transform (and T psi for GRAD).
+// fb: element offset of a frame (group) base, uniform across the block;
+// off: element offset from there; pix: pixel index inside the frame.
 template <int MODE>
-__device__ __forceinline__ void prologue2(const FrameArgs& A, int frame, int y, int x, size_t gidx, int pix,
-                                          float2& z0, float2& z1, float2& t0, float2& t1) {
+__device__ __forceinline__ void prologue2(const FrameArgs& A, int frame, int y, int x, size_t fb, unsigned off,
+                                          unsigned pix, float2& z0, float2& z1, float2& t0, float2& t1) {
     if constexpr (MODE == FM_RAAR) {
         float2 p0, p1, w0, w1;
-        ld2(A.u, gidx, z0, z1);
+        ld2(A.u + fb, off, z0, z1);
         gather2(A, frame, y, x, p0, p1);
         ld2(A.w_g, pix, w0, w1);
         z0 = cadd(z0, cscale(cmul(w0, p0), A.g));
         z1 = cadd(z1, cscale(cmul(w1, p1), A.g));
     } else if constexpr (MODE == FM_PA || MODE == FM_F || MODE == FM_FINV) {
-        ld2(A.in, gidx, z0, z1);
+        ld2(A.in + fb, off, z0, z1);
     } else {  // GRAD, SIM, Q
         float2 w0, w1;
         gather2(A, frame, y, x, t0, t1);
@@ -120,24 +145,29 @@ __device__ __forceinline__ void prologue2(const FrameArgs& A, int frame, int y, 
 // `addr_to_g` maps the LDS element address to (frame, global index).
 template <int MODE, int M>
 struct ModOp {
-    const float* __restrict__ a;
-    float* __restrict__ out_f;
+    const float* __restrict__ a;      // frame (group) base of the amplitudes
+    float* __restrict__ out_f;        // frame (group) base of the intensity output
     float resid = 0.f;
-    __device__ __forceinline__ void apply(bool ok, size_t gi, float2& v) {
+    // v is the unscaled transform value at element offset i from the bases
+    __device__ __forceinline__ void apply(bool ok, unsigned i, float2& v) {
         v = cscale(v, 1.0f / M);  // unitary scaling of F
         if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
-            const float av = ok ? a[gi] : 0.f;
-            const float n2 = cabs2(v);
-            const float mag = sqrtf(n2);
-            float2 s = make_float2(1.f, 0.f);  // sgn(0) := 1
-            if (n2 > 0.f) s = cscale(v, 1.0f / mag);
-            const float d = mag - av;
-            if (ok) resid += d * d;
-            const float2 p = cscale(s, av);
-            v = (MODE == FM_GRAD) ? csub(v, p) : p;
+            const float av = ok ? a[i] : 0.f;
+            v = modulus(v, av, ok);
         } else if constexpr (MODE == FM_SIM) {
-            if (ok) out_f[gi] = cabs2(v);
+            if (ok) out_f[i] = cabs2(v);
         }
+    }
+    // P_a on one value: a sgn(v), sgn(0) := 1; GRAD keeps v - a sgn(v)
+    __device__ __forceinline__ float2 modulus(float2 v, float av, bool ok) {
+        const float n2 = cabs2(v);
+        const float mag = sqrtf(n2);
+        float2 s = make_float2(1.f, 0.f);
+        if (n2 > 0.f) s = cscale(v, 1.0f / mag);
+        const float d = mag - av;
+        if (ok) resid += d * d;
+        const float2 p = cscale(s, av);
+        return (MODE == FM_GRAD) ? csub(v, p) : p;
     }
 };
 
@@ -170,17 +200,6 @@ struct FG {
     static constexpr size_t SMEM = (size_t)(LDS + M) * sizeof(float2);
 };
 
-template <int M, int MODE>
-struct FGPost {
-    ModOp<MODE, M> op;
-    int frame0, K;
-    __device__ __forceinline__ void operator()(int addr, float2& v) {
-        const int frame = frame0 + addr / (M * M);
-        const bool ok = frame < K;
-        op.apply(ok, (size_t)frame * M * M + addr % (M * M), v);
-    }
-};
-
 // fft_stage calls post(b, e, v); wrap to give the LDS element address instead.
 template <class Lay, class P>
 struct AddrPost {
@@ -208,22 +227,27 @@ __device__ __forceinline__ void fft_1d_post(float2* lds, const float2* twl, P& p
 }
 
 // One group of G frames: prologue -> F -> Fourier op -> F* -> epilogue.
-// Ends with a barrier, so the caller may reuse the LDS right away.
+// Every thread owns the element pairs e0 = 2 (tid + NT k) of the group for
+// the prologue, the Fourier-domain operation and the epilogue, so all global
+// accesses are coalesced and share one 32-bit offset per pair.  Ends with a
+// barrier, so the caller may reuse the LDS right away.
 template <int M, int MODE>
 __device__ __forceinline__ void fg_group(const FrameArgs& A, int grp, float2* lds, const float2* twl, float& resid,
                                          float2* gacc) {
+    const int tid = opaque_tid();
     using C = FG<M>;
     constexpr int NT = C::NT, G = C::G, NP = C::NP, MM = M * M;
+    const int f0 = grp * G;
+    const size_t fb = (size_t)f0 * MM;  // element offset of the group in frame stacks
     float2 z[2 * NP], t[2 * NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int e0 = 2 * (tid + NT * k);
         const int f = e0 / MM, rem = e0 % MM, y = rem / M, x = rem % M;
-        const int frame = grp * G + f;
+        const int frame = f0 + f;
         z[2 * k] = z[2 * k + 1] = t[2 * k] = t[2 * k + 1] = make_float2(0.f, 0.f);
         if (frame < A.K)
-            prologue2<MODE>(A, frame, y, x, (size_t)frame * MM + rem, rem, z[2 * k], z[2 * k + 1], t[2 * k],
-                            t[2 * k + 1]);
+            prologue2<MODE>(A, frame, y, x, fb, e0, rem, z[2 * k], z[2 * k + 1], t[2 * k], t[2 * k + 1]);
         lds[pidx(e0)] = z[2 * k];
         lds[pidx(e0 + 1)] = z[2 * k + 1];
     }
@@ -232,44 +256,52 @@ __device__ __forceinline__ void fg_group(const FrameArgs& A, int grp, float2* ld
     constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
     NoPost none;
     fft_1d<M, D1, NT, G * M, RowLay<M>>(lds, twl, none);
-    FGPost<M, MODE> post{{A.a, A.out_f, 0.f}, grp * G, A.K};
-    fft_1d_post<M, D1, NT, G * M, ColLayFG<M>>(lds, twl, post);
-    resid += post.op.resid;
-    if constexpr (MODE == FM_SIM) return;
-    if constexpr (MODE == FM_F || MODE == FM_FINV) {
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (threadIdx.x + NT * k);
-            const int f = e0 / MM, rem = e0 % MM, frame = grp * G + f;
-            if (frame < A.K) st2(A.out, (size_t)frame * MM + rem, lds[pidx(e0)], lds[pidx(e0 + 1)]);
-        }
-        __syncthreads();
-        return;
-    }
-    fft_1d<M, -1, NT, G * M, RowLay<M>>(lds, twl, none);
-    fft_1d<M, -1, NT, G * M, ColLayFG<M>>(lds, twl, none);
+    fft_1d<M, D1, NT, G * M, ColLayFG<M>>(lds, twl, none);
+
+    // Fourier-domain operation on the same element pairs
+    ModOp<MODE, M> op{A.a + fb, A.out_f + fb, 0.f};
     const float inv_m = 1.0f / M;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e0 = 2 * (threadIdx.x + NT * k);
-        const int f = e0 / MM, rem = e0 % MM, frame = grp * G + f;
+        const int e0 = 2 * (tid + NT * k);
+        const bool ok = f0 + e0 / MM < A.K;
+        float2 v0 = cscale(lds[pidx(e0)], inv_m), v1 = cscale(lds[pidx(e0 + 1)], inv_m);
+        if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
+            const float2 av = ok ? ldf2(A.a + fb, e0) : make_float2(0.f, 0.f);
+            lds[pidx(e0)] = op.modulus(v0, av.x, ok);
+            lds[pidx(e0 + 1)] = op.modulus(v1, av.y, ok);
+        } else if constexpr (MODE == FM_SIM) {
+            if (ok) stf2(A.out_f + fb, e0, cabs2(v0), cabs2(v1));
+        } else if constexpr (MODE == FM_F || MODE == FM_FINV) {
+            if (ok) st2(A.out + fb, e0, v0, v1);
+        }
+    }
+    resid += op.resid;
+    __syncthreads();
+    if constexpr (MODE == FM_SIM || MODE == FM_F || MODE == FM_FINV) return;
+
+    fft_1d<M, -1, NT, G * M, RowLay<M>>(lds, twl, none);
+    fft_1d<M, -1, NT, G * M, ColLayFG<M>>(lds, twl, none);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (tid + NT * k);
+        const int f = e0 / MM, rem = e0 % MM, frame = f0 + f;
         if (frame >= A.K) continue;
-        const size_t gi = (size_t)frame * MM + rem;
         const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
         if constexpr (MODE == FM_RAAR) {
             float2 w0, w1;
             ld2(A.w, rem, w0, w1);
             const float b = A.beta, c = 1.f - 2.f * A.beta;
-            st2(A.u, gi, cadd(cscale(z[2 * k], b), cscale(y0, c)), cadd(cscale(z[2 * k + 1], b), cscale(y1, c)));
-            st2(A.v, gi, cconjmul(w0, csub(cscale(y0, 2.f), z[2 * k])),
+            st2(A.u + fb, e0, cadd(cscale(z[2 * k], b), cscale(y0, c)), cadd(cscale(z[2 * k + 1], b), cscale(y1, c)));
+            st2(A.v + fb, e0, cconjmul(w0, csub(cscale(y0, 2.f), z[2 * k])),
                 cconjmul(w1, csub(cscale(y1, 2.f), z[2 * k + 1])));
         } else if constexpr (MODE == FM_PA) {
-            st2(A.out, gi, y0, y1);
+            st2(A.out + fb, e0, y0, y1);
         } else if constexpr (MODE == FM_GRAD) {
             float2 w0, w1;
             ld2(A.w, rem, w0, w1);
             const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
-            st2(A.v, gi, cconjmul(w0, r0), cconjmul(w1, r1));
+            st2(A.v + fb, e0, cconjmul(w0, r0), cconjmul(w1, r1));
             gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t[2 * k], r0));
             gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t[2 * k + 1], r1));
         }
@@ -303,7 +335,7 @@ __global__ void __launch_bounds__(FG<M>::NT) fg_kernel(FrameArgs A) {
         for (int k = 0; k < NP; ++k) {
             const int e0 = 2 * (threadIdx.x + NT * k);
             const int f = e0 / MM, rem = e0 % MM;
-            st2(A.gw_part, ((size_t)blockIdx.x * G + f) * MM + rem, gacc[2 * k], gacc[2 * k + 1]);
+            st2(A.gw_part + (size_t)blockIdx.x * G * MM, f * MM + rem, gacc[2 * k], gacc[2 * k + 1]);
         }
     }
 }
@@ -311,9 +343,9 @@ __global__ void __launch_bounds__(FG<M>::NT) fg_kernel(FrameArgs A) {
 // ---------------------------------------------------------------------------
 // m = 256: three passes through an HBM stage buffer
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, int NT_ = 256>
 struct MP {
-    static constexpr int NT = 256, E = 16, NP = E / 2;
+    static constexpr int NT = NT_, E = 16, NP = E / 2;
     static constexpr int RB = NT * E / M;  // rows per row-pass workgroup
     static constexpr int CB = NT * E / M;  // columns per column-pass workgroup
     static constexpr int NRB = M / RB, NCB = M / CB;
@@ -322,17 +354,18 @@ struct MP {
 };
 
 // Row pass forward on item it = frame * NRB + row block: prologue + row FFTs -> stage
-template <int M, int MODE>
+template <int M, int MODE, int NTB = 256>
 __device__ __forceinline__ void mp_row_fwd_item(const FrameArgs& A, int it, float2* lds, const float2* twl) {
-    using C = MP<M>;
+    const int tid = opaque_tid();
+    using C = MP<M, NTB>;
     constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = C::NRB;
     const int frame = it / NRB, rb = it % NRB;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int e0 = 2 * (tid + NT * k);
         const int y = rb * RB + e0 / M, x = e0 % M, rem = y * M + x;
         float2 z0, z1, t0, t1;
-        prologue2<MODE>(A, frame, y, x, (size_t)frame * MM + rem, rem, z0, z1, t0, t1);
+        prologue2<MODE>(A, frame, y, x, (size_t)frame * MM, rem, rem, z0, z1, t0, t1);
         lds[pidx(e0)] = z0;
         lds[pidx(e0 + 1)] = z1;
     }
@@ -342,55 +375,54 @@ __device__ __forceinline__ void mp_row_fwd_item(const FrameArgs& A, int it, floa
     fft_1d<M, D1, NT, RB, RowLay<M>>(lds, twl, none);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int e0 = 2 * (tid + NT * k);
         const int y = rb * RB + e0 / M, x = e0 % M;
-        st2(A.stage, (size_t)frame * MM + y * M + x, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+        st2(A.stage + (size_t)frame * MM, y * M + x, lds[pidx(e0)], lds[pidx(e0 + 1)]);
     }
     __syncthreads();
 }
 
-template <int M, int MODE>
-__global__ void __launch_bounds__(256) mp_row_fwd(FrameArgs A) {
-    using C = MP<M>;
+template <int M, int MODE, int NTB = 256>
+__global__ void __launch_bounds__(NTB) mp_row_fwd(FrameArgs A) {
+    using C = MP<M, NTB>;
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* twl = smem + C::LDS;
     for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = A.tw[t];
     const int items = A.K * C::NRB;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) mp_row_fwd_item<M, MODE>(A, it, lds, twl);
+    for (int it = blockIdx.x; it < items; it += gridDim.x) mp_row_fwd_item<M, MODE, NTB>(A, it, lds, twl);
 }
 
-template <int M, int MODE>
+template <int M, int MODE, int NTB = 256>
 struct CBPost {
-    ModOp<MODE, M> op;
-    size_t fbase;
-    int x0;
+    ModOp<MODE, M> op;  // bases point at the frame's column block
     __device__ __forceinline__ void operator()(int addr, float2& v) {
-        constexpr int CB = MP<M>::CB;
-        op.apply(true, fbase + (size_t)(addr / CB) * M + x0 + addr % CB, v);
+        constexpr int CB = MP<M, NTB>::CB;
+        op.apply(true, (unsigned)((addr / CB) * M + addr % CB), v);
     }
 };
 
 // Column pass on item it = frame * NCB + column block: column FFTs + Fourier op
 // (+ inverse column FFTs); returns this thread's residual contribution.
-template <int M, int MODE>
+template <int M, int MODE, int NTB = 256>
 __device__ __forceinline__ float mp_col_item(const FrameArgs& A, int it, float2* lds, const float2* twl) {
-    using C = MP<M>;
+    const int tid = opaque_tid();
+    using C = MP<M, NTB>;
     constexpr int NT = C::NT, NP = C::NP, CB = C::CB, MM = M * M, NCB = C::NCB;
     const int frame = it / NCB, cb = it % NCB;
     const size_t fb = (size_t)frame * MM;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int e0 = 2 * (tid + NT * k);
         const int y = e0 / CB, c = e0 % CB;
         float2 a0, a1;
-        ld2(A.stage, fb + (size_t)y * M + cb * CB + c, a0, a1);
+        ld2(A.stage + fb, y * M + cb * CB + c, a0, a1);
         lds[pidx(e0)] = a0;
         lds[pidx(e0 + 1)] = a1;
     }
     __syncthreads();
     constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
-    CBPost<M, MODE> post{{A.a, A.out_f, 0.f}, fb, cb * CB};
+    CBPost<M, MODE, NTB> post{{A.a + fb + cb * CB, A.out_f + fb + cb * CB, 0.f}};
     fft_1d_post<M, D1, NT, CB, ColLayCB<CB>>(lds, twl, post);
     if constexpr (MODE == FM_SIM) return post.op.resid;
     float2* dst = A.stage;
@@ -402,17 +434,17 @@ __device__ __forceinline__ float mp_col_item(const FrameArgs& A, int it, float2*
     }
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int e0 = 2 * (tid + NT * k);
         const int y = e0 / CB, c = e0 % CB;
-        st2(dst, fb + (size_t)y * M + cb * CB + c, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+        st2(dst + fb, y * M + cb * CB + c, lds[pidx(e0)], lds[pidx(e0 + 1)]);
     }
     __syncthreads();
     return post.op.resid;
 }
 
-template <int M, int MODE>
-__global__ void __launch_bounds__(256) mp_col(FrameArgs A) {
-    using C = MP<M>;
+template <int M, int MODE, int NTB = 256>
+__global__ void __launch_bounds__(NTB) mp_col(FrameArgs A) {
+    using C = MP<M, NTB>;
     extern __shared__ float2 smem[];
     __shared__ float red[C::NT / 64];
     float2* lds = smem;
@@ -420,7 +452,7 @@ __global__ void __launch_bounds__(256) mp_col(FrameArgs A) {
     for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = A.tw[t];
     float resid = 0.f;
     const int items = A.K * C::NCB;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) resid += mp_col_item<M, MODE>(A, it, lds, twl);
+    for (int it = blockIdx.x; it < items; it += gridDim.x) resid += mp_col_item<M, MODE, NTB>(A, it, lds, twl);
     if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
         const float s = block_sum(resid, red);
         if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
@@ -428,19 +460,20 @@ __global__ void __launch_bounds__(256) mp_col(FrameArgs A) {
 }
 
 // Row pass inverse on item it: inverse row FFTs + epilogue
-template <int M, int MODE>
+template <int M, int MODE, int NTB = 256>
 __device__ __forceinline__ void mp_row_inv_item(const FrameArgs& A, int it, float2* lds, const float2* twl,
                                                 float2* gacc) {
-    using C = MP<M>;
+    const int tid = opaque_tid();
+    using C = MP<M, NTB>;
     constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = C::NRB;
     const int frame = it / NRB, rb = it % NRB;
     const size_t fb = (size_t)frame * MM;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int e0 = 2 * (tid + NT * k);
         const int y = rb * RB + e0 / M, x = e0 % M;
         float2 a0, a1;
-        ld2(A.stage, fb + (size_t)y * M + x, a0, a1);
+        ld2(A.stage + fb, y * M + x, a0, a1);
         lds[pidx(e0)] = a0;
         lds[pidx(e0 + 1)] = a1;
     }
@@ -450,25 +483,24 @@ __device__ __forceinline__ void mp_row_inv_item(const FrameArgs& A, int it, floa
     const float inv_m = 1.0f / M;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e0 = 2 * (threadIdx.x + NT * k);
+        const int e0 = 2 * (tid + NT * k);
         const int y = rb * RB + e0 / M, x = e0 % M, rem = y * M + x;
-        const size_t gi = fb + rem;
         const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
         if constexpr (MODE == FM_RAAR) {
             float2 z0, z1, t0, t1, w0, w1;
-            prologue2<MODE>(A, frame, y, x, gi, rem, z0, z1, t0, t1);
+            prologue2<MODE>(A, frame, y, x, fb, rem, rem, z0, z1, t0, t1);
             ld2(A.w, rem, w0, w1);
             const float b = A.beta, c = 1.f - 2.f * A.beta;
-            st2(A.u, gi, cadd(cscale(z0, b), cscale(y0, c)), cadd(cscale(z1, b), cscale(y1, c)));
-            st2(A.v, gi, cconjmul(w0, csub(cscale(y0, 2.f), z0)), cconjmul(w1, csub(cscale(y1, 2.f), z1)));
+            st2(A.u + fb, rem, cadd(cscale(z0, b), cscale(y0, c)), cadd(cscale(z1, b), cscale(y1, c)));
+            st2(A.v + fb, rem, cconjmul(w0, csub(cscale(y0, 2.f), z0)), cconjmul(w1, csub(cscale(y1, 2.f), z1)));
         } else if constexpr (MODE == FM_PA) {
-            st2(A.out, gi, y0, y1);
+            st2(A.out + fb, rem, y0, y1);
         } else if constexpr (MODE == FM_GRAD) {
             float2 t0, t1, w0, w1;
             gather2(A, frame, y, x, t0, t1);
             ld2(A.w, rem, w0, w1);
             const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
-            st2(A.v, gi, cconjmul(w0, r0), cconjmul(w1, r1));
+            st2(A.v + fb, rem, cconjmul(w0, r0), cconjmul(w1, r1));
             gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t0, r0));
             gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t1, r1));
         }
@@ -476,9 +508,9 @@ __device__ __forceinline__ void mp_row_inv_item(const FrameArgs& A, int it, floa
     __syncthreads();
 }
 
-template <int M, int MODE>
-__global__ void __launch_bounds__(256) mp_row_inv(FrameArgs A) {
-    using C = MP<M>;
+template <int M, int MODE, int NTB = 256>
+__global__ void __launch_bounds__(NTB) mp_row_inv(FrameArgs A) {
+    using C = MP<M, NTB>;
     constexpr int NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = C::NRB;
     extern __shared__ float2 smem[];
     float2* lds = smem;
@@ -488,7 +520,7 @@ __global__ void __launch_bounds__(256) mp_row_inv(FrameArgs A) {
 #pragma unroll
     for (int i = 0; i < 2 * NP; ++i) gacc[i] = make_float2(0.f, 0.f);
     const int items = A.K * NRB;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) mp_row_inv_item<M, MODE>(A, it, lds, twl, gacc);
+    for (int it = blockIdx.x; it < items; it += gridDim.x) mp_row_inv_item<M, MODE, NTB>(A, it, lds, twl, gacc);
     if constexpr (MODE == FM_GRAD) {
         // gridDim.x is a multiple of NRB, so this block only saw row block blockIdx.x % NRB.
         const int slot = blockIdx.x / NRB, rb = blockIdx.x % NRB;
@@ -496,7 +528,7 @@ __global__ void __launch_bounds__(256) mp_row_inv(FrameArgs A) {
         for (int k = 0; k < NP; ++k) {
             const int e0 = 2 * (threadIdx.x + NT * k);
             const int y = rb * RB + e0 / M, x = e0 % M;
-            st2(A.gw_part, (size_t)slot * MM + y * M + x, gacc[2 * k], gacc[2 * k + 1]);
+            st2(A.gw_part + (size_t)slot * MM, y * M + x, gacc[2 * k], gacc[2 * k + 1]);
         }
     }
 }
@@ -512,8 +544,8 @@ __global__ void __launch_bounds__(256) q_kernel(FrameArgs A) {
         const size_t e0 = 2 * i;
         const int frame = (int)(e0 / MM), rem = (int)(e0 % MM), y = rem / M, x = rem % M;
         float2 z0, z1, t0, t1;
-        prologue2<FM_Q>(A, frame, y, x, e0, rem, z0, z1, t0, t1);
-        st2(A.out, e0, z0, z1);
+        prologue2<FM_Q>(A, frame, y, x, 0, 0, rem, z0, z1, t0, t1);
+        st2(A.out + e0, 0, z0, z1);
     }
 }
 
@@ -538,22 +570,45 @@ static hipError_t launch_fg(const FrameArgs& A, int grid, hipStream_t s, const T
     return hipGetLastError();
 }
 
-template <int M, int MODE>
+template <int M, int MODE, int NTB = 256>
 static hipError_t launch_mp(const FrameArgs& A, int grid_rows, int grid_cols, int grid_inv, hipStream_t s,
                             const Timer& t) {
-    using C = MP<M>;
+    using C = MP<M, NTB>;
     t.begin(TC_FRAME);
-    hipLaunchKernelGGL((mp_row_fwd<M, MODE>), dim3(grid_rows), dim3(C::NT), C::SMEM, s, A);
+    hipLaunchKernelGGL((mp_row_fwd<M, MODE, NTB>), dim3(grid_rows), dim3(NTB), C::SMEM, s, A);
     t.end(TC_FRAME);
     t.begin(TC_COLS);
-    hipLaunchKernelGGL((mp_col<M, MODE>), dim3(grid_cols), dim3(C::NT), C::SMEM, s, A);
+    hipLaunchKernelGGL((mp_col<M, MODE, NTB>), dim3(grid_cols), dim3(NTB), C::SMEM, s, A);
     t.end(TC_COLS);
     if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
         t.begin(TC_FRAME_OUT);
-        hipLaunchKernelGGL((mp_row_inv<M, MODE>), dim3(grid_inv), dim3(C::NT), C::SMEM, s, A);
+        hipLaunchKernelGGL((mp_row_inv<M, MODE, NTB>), dim3(grid_inv), dim3(NTB), C::SMEM, s, A);
         t.end(TC_FRAME_OUT);
     }
     return hipGetLastError();
+}
+
+// RAAR frame phase for m = 256 with a chosen pass block (threads 128, 256 or
+// 512: 8, 16 or 32 rows / columns per workgroup).
+hipError_t launch_raar_mp256(const FrameArgs& A, int threads, hipStream_t s, const Timer* tp, int* blocks_used) {
+    const Timer& t = tp ? *tp : kNoTimer;
+    switch (threads) {
+        case 128: {
+            const int items = A.K * MP<256, 128>::NRB;
+            *blocks_used = A.K * MP<256, 128>::NCB;
+            return launch_mp<256, FM_RAAR, 128>(A, items, *blocks_used, items, s, t);
+        }
+        case 512: {
+            const int items = A.K * MP<256, 512>::NRB;
+            *blocks_used = A.K * MP<256, 512>::NCB;
+            return launch_mp<256, FM_RAAR, 512>(A, items, *blocks_used, items, s, t);
+        }
+        default: {
+            const int items = A.K * MP<256, 256>::NRB;
+            *blocks_used = A.K * MP<256, 256>::NCB;
+            return launch_mp<256, FM_RAAR, 256>(A, items, *blocks_used, items, s, t);
+        }
+    }
 }
 
 template <int M>
@@ -807,6 +862,121 @@ hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* 
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// m = 256 in one persistent launch, XCD-local.
+//
+// Frame f belongs to XCD (f mod nq).  The blocks running on an XCD take
+// tickets from that XCD's queue, which interleaves the three passes of its
+// frames with a lag of L frames: row pass of frame i, column pass of frame
+// i - L, output row pass of frame i - 2L.  A column (output) item starts once
+// all 16 row (column) items of its frame are done.  Producer and consumer of
+// a frame's stage data therefore share one L2: the producer waits for its
+// stores to complete and bumps a per-frame counter (an L2 atomic); the
+// consumer sees the count, drops its CU's L1 lines and reads through L2.  No
+// device-wide cache write-back is needed.  A block only ever waits for
+// tickets taken earlier by running blocks, so the queue always drains; every
+// wait is bounded and reports through the error flag if it expires.
+// ---------------------------------------------------------------------------
+struct XfSync {
+    int* tickets;   // [nq]
+    int* doneA;     // [K] row items finished
+    int* doneB;     // [K] column items finished
+    int* doneC;     // [1] output items finished (completeness check)
+    int* flag;      // error flag (slot 1 = incomplete / expired wait)
+    int nq, lag;
+};
+
+__device__ __forceinline__ int xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15;  // HW_REG_XCC_ID[3:0]
+}
+
+__device__ __forceinline__ void stores_done_then_count(int* ctr) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores reached L2
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void wait_count(const int* ctr, int target, int* flag) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            // bounded: ~1e6 polls (tens of ms); once any wait has expired the
+            // rest give up at once, so a broken queue cannot stall the launch
+            if (++spins > (1 << 20) || __hip_atomic_load(&flag[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                flag[1] = 1;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    asm volatile("buffer_inv sc0" ::: "memory");  // drop this CU's L1 lines: reads go to L2
+}
+
+__global__ void __launch_bounds__(256) xf_kernel_256(FrameArgs A, XfSync S) {
+    constexpr int M = 256, NI = 16;  // items per frame and pass
+    using C = MP<M>;
+    extern __shared__ float2 smem[];
+    __shared__ float red[C::NT / 64];
+    __shared__ int tk;
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = A.tw[t];
+    const int q = xcc_id() % S.nq;
+    const int nf = (A.K - q + S.nq - 1) / S.nq;  // frames q, q + nq, ...
+    const int total = (nf + 2 * S.lag) * 3 * NI;
+    while (true) {
+        if (threadIdx.x == 0) tk = atomicAdd(&S.tickets[q], 1);
+        __syncthreads();
+        const int t = tk;
+        __syncthreads();
+        if (t >= total) break;
+        const int slot = t / (3 * NI), r = t % (3 * NI), pass = r / NI, piece = r % NI;
+        const int i = slot - pass * S.lag;
+        if (i < 0 || i >= nf) continue;
+        const int f = q + i * S.nq;
+        const int it = f * NI + piece;
+        if (pass == 0) {
+            mp_row_fwd_item<M, FM_RAAR>(A, it, lds, twl);
+            stores_done_then_count(&S.doneA[f]);
+        } else if (pass == 1) {
+            wait_count(&S.doneA[f], NI, S.flag);
+            const float s = block_sum(mp_col_item<M, FM_RAAR>(A, it, lds, twl), red);
+            if (threadIdx.x == 0) A.resid[it] = s;
+            stores_done_then_count(&S.doneB[f]);
+        } else {
+            wait_count(&S.doneB[f], NI, S.flag);
+            mp_row_inv_item<M, FM_RAAR>(A, it, lds, twl, nullptr);
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(S.doneC, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void xf_check_kernel(const int* doneC, int expect, int* flag) {
+    if (threadIdx.x == 0 && doneC[0] != expect) flag[1] = 1;
+}
+
+int xf_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xf_kernel_256, 256, MP<256>::SMEM) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_xf_256(const FrameArgs& A, int* sync_base, int* flag, int nq, int grid, hipStream_t s,
+                         const Timer* t) {
+    // counters: tickets [16], doneC [16], doneA [K], doneB [K]
+    XfSync S{sync_base, sync_base + 32, sync_base + 32 + A.K, sync_base + 16, flag, nq, 0};
+    const int per_q = std::max(1, grid / nq);
+    S.lag = (per_q + 3 * 16 - 1) / (3 * 16) + 1;
+    hipError_t e = launch_fill(sync_base, (32 + 2 * (size_t)A.K) * sizeof(int), s);
+    if (e != hipSuccess) return e;
+    if (t) t->begin(TC_FRAME);
+    hipLaunchKernelGGL(xf_kernel_256, dim3(grid), dim3(256), MP<256>::SMEM, s, A, S);
+    if (t) t->end(TC_FRAME);
+    hipLaunchKernelGGL(xf_check_kernel, dim3(1), dim3(64), 0, s, (const int*)S.doneC, A.K * 16, flag);
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
 
 struct Offsets {
     size_t tw, pos, tile_ptr, tile_frames, a, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
-    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, total;
+    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, xsync, total;
 };
 
 }  // namespace sharp
@@ -32,6 +32,9 @@ struct sharp_plan_s {
     sharp_options opt{};
     std::vector<int32_t> pos;
     int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
+    int frame_launch = 1;     // m = 256: 1 = three launches, 2 = persistent XCD-local launch
+    int fft_block = 256;      // m = 256, three launches: threads per pass workgroup
+    int xf_grid = 0, xf_nq = 0;  // persistent launch: blocks and XCD queues (0 = unavailable)
     std::vector<int32_t> tile_ptr, tile_frames;
     sharp::Offsets off{};
     size_t resid_cap = 0, gw_slots = 0;
@@ -71,4 +74,6 @@ FrameArgs frame_args(const sharp_plan_s& p);
 MergeArgs merge_args(const sharp_plan_s& p);
 // number of per-block residual partials an iteration's frame launch writes
 int resid_blocks(const sharp_plan_s& p);
+// the same for the default launch shape (used by batched execution)
+int resid_blocks_default(const sharp_plan_s& p);
 }  // namespace sharp

@@ -51,6 +51,7 @@ extern "C" const char* sharp_status_string(int s) {
         case SHARP_ERR_NONFINITE: return "non-finite value in data or iterate";
         case SHARP_ERR_HIP: return "HIP runtime error";
         case SHARP_ERR_HOST_ALLOC: return "host allocation failed";
+        case SHARP_ERR_DEVICE_WAIT: return "a bounded device-side wait expired; work was left undone";
     }
     return "unknown status";
 }
@@ -114,6 +115,8 @@ static void choose_tuning(sharp_plan_s& p) {
     else p.grad_groups = (p.m == 256) ? 1024 : std::min(groups, p.m == 128 ? 256 : 512);
     if (p.m == 256) p.grad_groups = std::max(16, p.grad_groups / 16 * 16);
     p.probe_chunks = std::min(p.K, 128);
+    p.frame_launch = p.opt.frame_launch ? p.opt.frame_launch : 1;
+    p.fft_block = p.opt.fft_block ? p.opt.fft_block : 256;
 }
 
 static void layout(sharp_plan_s& p) {
@@ -147,12 +150,13 @@ static void layout(sharp_plan_s& p) {
     o.pden = take((size_t)p.probe_chunks * MM * sizeof(float));
     p.gw_slots = frame_partial_slots(p.m, FM_GRAD, p.m == 256 ? p.grad_groups : p.grad_groups);
     o.gwpart = take(std::max<size_t>(p.gw_slots, 1) * MM * sizeof(float2));
-    const size_t groups = (p.m == 256) ? (size_t)p.K * 16 : (size_t)(p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
+    const size_t groups = (p.m == 256) ? (size_t)p.K * 32 : (size_t)(p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
     p.resid_cap = std::max<size_t>(groups, 2048);
     o.resid = take(p.resid_cap * sizeof(float));
     o.hist = take(kHistCap * sizeof(float));
     o.scal = take(16 * sizeof(float));
     o.flag = take(16 * sizeof(int));
+    o.xsync = take(p.m == 256 ? (32 + 2 * (size_t)p.K) * sizeof(int) : 0);
     o.total = cur;
 }
 
@@ -162,7 +166,8 @@ extern "C" int sharp_plan_create(sharp_plan* out, int nx, int ny, int m, int K, 
     *out = nullptr;
     if (K < 1 || nx < 1 || ny < 1) return SHARP_ERR_INVALID_ARG;
     if (!supported_m(m) || m > nx || m > ny) return SHARP_ERR_UNSUPPORTED_SIZE;
-    if ((long long)K * m * m > 2147483647LL || (long long)nx * ny > 2147483647LL) return SHARP_ERR_UNSUPPORTED_SIZE;
+    // frame stacks index with 32-bit element counts; objects with 32-bit byte offsets
+    if ((long long)K * m * m > 2147483647LL || (long long)nx * ny > (1LL << 28)) return SHARP_ERR_UNSUPPORTED_SIZE;
     sharp_options o{};
     if (opt) {
         o = *opt;
@@ -170,7 +175,8 @@ extern "C" int sharp_plan_create(sharp_plan* out, int nx, int ny, int m, int K, 
             if (r != 0) return SHARP_ERR_INVALID_ARG;
         if (o.periodic < 0 || o.periodic > 1 || o.probe_every < 0 || o.probe_start < 0 || !(o.eps_D >= 0.f) ||
             !(o.tile == 0 || o.tile == 16 || o.tile == 32 || o.tile == 64) || o.merge_split < 0 ||
-            o.merge_split > 4096 || o.grad_groups < 0)
+            o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 2 ||
+            !(o.fft_block == 0 || o.fft_block == 128 || o.fft_block == 256 || o.fft_block == 512))
             return SHARP_ERR_INVALID_ARG;
     }
     if (o.probe_start == 0) o.probe_start = 1;
@@ -238,6 +244,17 @@ extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
         HIPCHK(hipMemcpyAsync(p->ws + p->off.tile_frames, p->tile_frames.data(),
                               p->tile_frames.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(launch_fill(p->ws + p->off.flag, 16 * sizeof(int), s));
+    if (p->m == 256) {
+        int dev = 0, cus = 0, xcc = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || xcc < 1 || xcc > 16)
+            xcc = 0;
+        (void)hipGetLastError();
+        p->xf_nq = xcc;
+        p->xf_grid = xcc ? xf_blocks_per_cu() * cus : 0;
+        if (!p->xf_nq && p->frame_launch == 2) p->frame_launch = 1;
+    }
     HIPCHK(launch_fill(p->ws + p->off.hist, kHistCap * sizeof(float), s));
     // host vectors are locals: finish the uploads before returning
     HIPCHK(hipStreamSynchronize(s));
@@ -297,8 +314,13 @@ MergeArgs sharp::merge_args(const sharp_plan_s& p) {
     return A;
 }
 
-int sharp::resid_blocks(const sharp_plan_s& p) {
+int sharp::resid_blocks_default(const sharp_plan_s& p) {
     return p.m == 256 ? p.K * 16 : (p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
+}
+
+int sharp::resid_blocks(const sharp_plan_s& p) {
+    if (p.m == 256 && p.frame_launch == 1) return p.K * (4096 / p.fft_block);
+    return resid_blocks_default(p);
 }
 
 static int density(sharp_plan_s& p) {
@@ -381,7 +403,14 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     A.beta = beta;
     int blocks = 0;
     const Timer* t = p.tm();
-    HIPCHK(launch_frame(FM_RAAR, A, 0, s, &blocks, t));
+    if (p.m == 256 && p.frame_launch == 2) {
+        HIPCHK(launch_xf_256(A, p.at<int>(p.off.xsync), p.at<int>(p.off.flag), p.xf_nq, p.xf_grid, s, t));
+        blocks = p.K * 16;
+    } else if (p.m == 256) {
+        HIPCHK(launch_raar_mp256(A, p.fft_block, s, t, &blocks));
+    } else {
+        HIPCHK(launch_frame(FM_RAAR, A, 0, s, &blocks, t));
+    }
     if (p.gat_stale) {
         HIPCHK(launch_copy(p.ws + p.off.w_gat, p.ws + p.off.w_cur, (size_t)p.m * p.m * sizeof(float2), s));
         p.gat_stale = false;
@@ -447,10 +476,11 @@ extern "C" int sharp_get_probe(sharp_plan p, void* d_out) {
 }
 
 static int read_flag(sharp_plan_s& p) {
-    int flag = 0;
-    HIPCHK(hipMemcpyAsync(&flag, p.ws + p.off.flag, sizeof(int), hipMemcpyDeviceToHost, p.stream));
+    int flag[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(flag, p.ws + p.off.flag, sizeof(flag), hipMemcpyDeviceToHost, p.stream));
     HIPCHK(hipStreamSynchronize(p.stream));
-    return flag ? SHARP_ERR_NONFINITE : SHARP_OK;
+    if (flag[1]) return SHARP_ERR_DEVICE_WAIT;
+    return flag[0] ? SHARP_ERR_NONFINITE : SHARP_OK;
 }
 
 extern "C" int sharp_sync(sharp_plan p) {
@@ -656,6 +686,8 @@ extern "C" int sharp_get_plan_info(sharp_plan p, sharp_plan_info* info) {
     info->tiles_y = p->tiles_y;
     info->merge_split = p->split;
     info->grad_groups = p->grad_groups;
+    info->frame_launch = p->frame_launch;
+    info->fft_block = p->fft_block;
     info->csr_nnz = (long long)p->tile_frames.size();
     info->iteration = p->iter;
     return SHARP_OK;

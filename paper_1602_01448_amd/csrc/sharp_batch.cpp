@@ -85,7 +85,7 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
             sharp_plan_s* p = plans[s];
             b->plans.push_back(p);
             const int mc = m_class(p->m);
-            const int items = resid_blocks(*p);  // frame groups (m <= 128) or frame row blocks (m = 256)
+            const int items = resid_blocks_default(*p);  // frame groups (m <= 128) or row blocks (m = 256)
             for (int it = 0; it < items; ++it) b->frame_items[mc].push_back(make_int2(s, it));
             const int tc = t_class(p->T);
             for (int t = 0; t < p->ntiles; ++t)
@@ -153,7 +153,7 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         sharp_plan_s& p = *b->plans[s];
         fa[s] = frame_args(p);
         ma[s] = merge_args(p);
-        ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks(p), 0, p.at<float>(p.off.scal),
+        ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),
                         p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
     }
     hipStream_t st = b->own;

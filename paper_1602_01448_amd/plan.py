@@ -32,7 +32,7 @@ class Plan:
 
     def __init__(self, nx: int, ny: int, m: int, positions, periodic: bool = False, probe_every: int = 0,
                  probe_start: int = 1, eps_D: float = 0.0, tile: int = 0, merge_split: int = 0,
-                 grad_groups: int = 0, device="cuda"):
+                 grad_groups: int = 0, frame_launch: int = 0, fft_block: int = 0, device="cuda"):
         pos = np.ascontiguousarray(np.asarray(positions), dtype=np.int32)
         if pos.ndim != 2 or pos.shape[1] != 2:
             raise ValueError("positions must be (K, 2) (y, x)")
@@ -41,7 +41,7 @@ class Plan:
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         opts = SharpOptions(int(periodic), int(probe_every), int(probe_start), float(eps_D), int(tile),
-                            int(merge_split), int(grad_groups))
+                            int(merge_split), int(grad_groups), int(frame_launch), int(fft_block))
         h = c_void_p()
         check(lib.sharp_plan_create(byref(h), self.nx, self.ny, self.m, self.K,
                                     pos.ctypes.data_as(POINTER(c_int32)), byref(opts)), "sharp_plan_create")
@@ -51,6 +51,15 @@ class Plan:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream()
         check(lib.sharp_set_workspace(h, _ptr(self.workspace), nbytes), "sharp_set_workspace")
+
+    @classmethod
+    def tuned(cls, nx: int, ny: int, m: int, positions, kind: str = "raar", periodic: bool = False, **kw):
+        """A plan with the launch options the autotuner stored for this geometry
+        (library defaults when the geometry has not been tuned)."""
+        from .autotune import lookup
+        opts = dict(lookup(kind, nx, ny, m, positions, periodic))
+        opts.update(kw)
+        return cls(nx, ny, m, positions, periodic=periodic, **opts)
 
     # -- plumbing ---------------------------------------------------------
     @property

@@ -40,7 +40,8 @@ def _create(L, n, m, pos, **kw):
     h = ctypes.c_void_p()
     pos = np.ascontiguousarray(pos, dtype=np.int32)
     opts = SharpOptions(kw.get("periodic", 0), kw.get("probe_every", 0), kw.get("probe_start", 1),
-                        kw.get("eps_D", 0.0), kw.get("tile", 0), kw.get("merge_split", 0), kw.get("grad_groups", 0))
+                        kw.get("eps_D", 0.0), kw.get("tile", 0), kw.get("merge_split", 0), kw.get("grad_groups", 0),
+                        kw.get("frame_launch", 0), kw.get("fft_block", 0))
     if "reserved" in kw:
         opts.reserved[0] = kw["reserved"]
     st = L.sharp_plan_create(ctypes.byref(h), n, n, m, len(pos), pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -49,7 +50,7 @@ def _create(L, n, m, pos, **kw):
 
 
 def test_status_strings(L):
-    for s in range(-8, 1):
+    for s in range(-9, 1):
         assert len(L.sharp_status_string(s)) > 0
     assert L.sharp_status_string(-99) == b"unknown status"
 
@@ -72,6 +73,9 @@ def test_validation(L):
     assert _create(L, 64, 32, [(0, 0)], tile=24)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], reserved=1)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], eps_D=-1.0)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], frame_launch=3)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], fft_block=64)[0] == -1
+    assert _create(L, 300, 256, [(0, 0)], fft_block=512)[0] == 0
     h = ctypes.c_void_p()
     assert L.sharp_plan_create(ctypes.byref(h), 64, 64, 32, 0, None, None) == -1
     assert L.sharp_plan_create(None, 64, 64, 32, 1, None, None) == -1
