@@ -45,7 +45,7 @@ def algorithmic_bytes(K: int, m: int, n: int) -> dict:
     }
 
 
-def gpu_workload(steps: int, warmup: int, timing: bool, frame_launch: int = 0):
+def gpu_workload(steps: int, warmup: int, timing: bool, fft_block: int = 0):
     import numpy as np
     import torch
 
@@ -54,7 +54,7 @@ def gpu_workload(steps: int, warmup: int, timing: bool, frame_launch: int = 0):
 
     dev = torch.device("cuda", 0)
     s = gen.config_scan(3)
-    plan = Plan(s.n, s.n, s.m, s.positions, frame_launch=frame_launch, device=dev)
+    plan = Plan.tuned(s.n, s.n, s.m, s.positions, device=dev, **({"fft_block": fft_block} if fft_block else {}))
     obj = torch.from_numpy(s.obj.astype(np.complex64)).to(dev)
     probe = torch.from_numpy(s.probe.astype(np.complex64)).to(dev)
     I = plan.simulate(obj, probe)
@@ -192,8 +192,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not bracket kernels with HIP events")
     ap.add_argument("--no-forms", action="store_true", help="skip the gradient and batched comparisons")
-    ap.add_argument("--frame-launch", type=int, default=0, choices=(0, 1, 2),
-                    help="m=256 frame phase: 0 library default, 1 three launches, 2 one persistent launch")
+    ap.add_argument("--fft-block", type=int, default=0, choices=(0, 128, 256, 512),
+                    help="m=256 pass workgroup threads (0: tuned or library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -202,7 +202,7 @@ def main() -> int:
 
     import torch
 
-    s, plan, ms, kt, eps = gpu_workload(args.steps, args.warmup, not args.no_timing, args.frame_launch)
+    s, plan, ms, kt, eps = gpu_workload(args.steps, args.warmup, not args.no_timing, args.fft_block)
     plan.sync()
     ms_step = ms / args.steps
     fps = s.K / (ms_step / 1e3)
@@ -223,7 +223,8 @@ def main() -> int:
         "config": {"workload": "large-frame RAAR: object 2048x2048, 2025 frames 256x256, step 40 jitter 2, "
                                "1e8 photons/frame, beta 0.75, known probe",
                    "object": s.n, "frame": s.m, "frames": s.K, "beta": s.beta,
-                   "frame_launch": plan.info()["frame_launch"]},
+                   "fft_block": plan.info()["fft_block"], "merge_tile": plan.info()["tile"],
+                   "merge_split": plan.info()["merge_split"]},
         "achieved_alg_GBps": round(B["iteration"] / (ms_step / 1e3) / 1e9, 1),
         "alg_frac_of_hbm_peak": round(B["iteration"] / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
         "eps_a_last": float(eps[-1]) if len(eps) else None,

@@ -865,119 +865,4 @@ hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* 
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// m = 256 in one persistent launch, XCD-local.
-//
-// Frame f belongs to XCD (f mod nq).  The blocks running on an XCD take
-// tickets from that XCD's queue, which interleaves the three passes of its
-// frames with a lag of L frames: row pass of frame i, column pass of frame
-// i - L, output row pass of frame i - 2L.  A column (output) item starts once
-// all 16 row (column) items of its frame are done.  Producer and consumer of
-// a frame's stage data therefore share one L2: the producer waits for its
-// stores to complete and bumps a per-frame counter (an L2 atomic); the
-// consumer sees the count, drops its CU's L1 lines and reads through L2.  No
-// device-wide cache write-back is needed.  A block only ever waits for
-// tickets taken earlier by running blocks, so the queue always drains; every
-// wait is bounded and reports through the error flag if it expires.
-// ---------------------------------------------------------------------------
-struct XfSync {
-    int* tickets;   // [nq]
-    int* doneA;     // [K] row items finished
-    int* doneB;     // [K] column items finished
-    int* doneC;     // [1] output items finished (completeness check)
-    int* flag;      // error flag (slot 1 = incomplete / expired wait)
-    int nq, lag;
-};
-
-__device__ __forceinline__ int xcc_id() {
-    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15;  // HW_REG_XCC_ID[3:0]
-}
-
-__device__ __forceinline__ void stores_done_then_count(int* ctr) {
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores reached L2
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void wait_count(const int* ctr, int target, int* flag) {
-    if (threadIdx.x == 0) {
-        int spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
-            // bounded: ~1e6 polls (tens of ms); once any wait has expired the
-            // rest give up at once, so a broken queue cannot stall the launch
-            if (++spins > (1 << 20) || __hip_atomic_load(&flag[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                flag[1] = 1;
-                break;
-            }
-        }
-    }
-    __syncthreads();
-    asm volatile("buffer_inv sc0" ::: "memory");  // drop this CU's L1 lines: reads go to L2
-}
-
-__global__ void __launch_bounds__(256) xf_kernel_256(FrameArgs A, XfSync S) {
-    constexpr int M = 256, NI = 16;  // items per frame and pass
-    using C = MP<M>;
-    extern __shared__ float2 smem[];
-    __shared__ float red[C::NT / 64];
-    __shared__ int tk;
-    float2* lds = smem;
-    float2* twl = smem + C::LDS;
-    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = A.tw[t];
-    const int q = xcc_id() % S.nq;
-    const int nf = (A.K - q + S.nq - 1) / S.nq;  // frames q, q + nq, ...
-    const int total = (nf + 2 * S.lag) * 3 * NI;
-    while (true) {
-        if (threadIdx.x == 0) tk = atomicAdd(&S.tickets[q], 1);
-        __syncthreads();
-        const int t = tk;
-        __syncthreads();
-        if (t >= total) break;
-        const int slot = t / (3 * NI), r = t % (3 * NI), pass = r / NI, piece = r % NI;
-        const int i = slot - pass * S.lag;
-        if (i < 0 || i >= nf) continue;
-        const int f = q + i * S.nq;
-        const int it = f * NI + piece;
-        if (pass == 0) {
-            mp_row_fwd_item<M, FM_RAAR>(A, it, lds, twl);
-            stores_done_then_count(&S.doneA[f]);
-        } else if (pass == 1) {
-            wait_count(&S.doneA[f], NI, S.flag);
-            const float s = block_sum(mp_col_item<M, FM_RAAR>(A, it, lds, twl), red);
-            if (threadIdx.x == 0) A.resid[it] = s;
-            stores_done_then_count(&S.doneB[f]);
-        } else {
-            wait_count(&S.doneB[f], NI, S.flag);
-            mp_row_inv_item<M, FM_RAAR>(A, it, lds, twl, nullptr);
-            if (threadIdx.x == 0) __hip_atomic_fetch_add(S.doneC, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-__global__ void xf_check_kernel(const int* doneC, int expect, int* flag) {
-    if (threadIdx.x == 0 && doneC[0] != expect) flag[1] = 1;
-}
-
-int xf_blocks_per_cu() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xf_kernel_256, 256, MP<256>::SMEM) != hipSuccess) return 1;
-    return nb > 0 ? nb : 1;
-}
-
-hipError_t launch_xf_256(const FrameArgs& A, int* sync_base, int* flag, int nq, int grid, hipStream_t s,
-                         const Timer* t) {
-    // counters: tickets [16], doneC [16], doneA [K], doneB [K]
-    XfSync S{sync_base, sync_base + 32, sync_base + 32 + A.K, sync_base + 16, flag, nq, 0};
-    const int per_q = std::max(1, grid / nq);
-    S.lag = (per_q + 3 * 16 - 1) / (3 * 16) + 1;
-    hipError_t e = launch_fill(sync_base, (32 + 2 * (size_t)A.K) * sizeof(int), s);
-    if (e != hipSuccess) return e;
-    if (t) t->begin(TC_FRAME);
-    hipLaunchKernelGGL(xf_kernel_256, dim3(grid), dim3(256), MP<256>::SMEM, s, A, S);
-    if (t) t->end(TC_FRAME);
-    hipLaunchKernelGGL(xf_check_kernel, dim3(1), dim3(64), 0, s, (const int*)S.doneC, A.K * 16, flag);
-    return hipGetLastError();
-}
-
 }  // namespace sharp

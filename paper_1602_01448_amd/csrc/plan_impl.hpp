@@ -22,7 +22,7 @@ inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
 
 struct Offsets {
     size_t tw, pos, tile_ptr, tile_frames, a, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
-    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, xsync, total;
+    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, total;
 };
 
 }  // namespace sharp
@@ -32,9 +32,8 @@ struct sharp_plan_s {
     sharp_options opt{};
     std::vector<int32_t> pos;
     int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
-    int frame_launch = 1;     // m = 256: 1 = three launches, 2 = persistent XCD-local launch
+    int frame_launch = 1;     // m = 256: 1 = three launches (the only form)
     int fft_block = 256;      // m = 256, three launches: threads per pass workgroup
-    int xf_grid = 0, xf_nq = 0;  // persistent launch: blocks and XCD queues (0 = unavailable)
     std::vector<int32_t> tile_ptr, tile_frames;
     sharp::Offsets off{};
     size_t resid_cap = 0, gw_slots = 0;

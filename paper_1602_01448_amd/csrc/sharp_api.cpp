@@ -156,7 +156,6 @@ static void layout(sharp_plan_s& p) {
     o.hist = take(kHistCap * sizeof(float));
     o.scal = take(16 * sizeof(float));
     o.flag = take(16 * sizeof(int));
-    o.xsync = take(p.m == 256 ? (32 + 2 * (size_t)p.K) * sizeof(int) : 0);
     o.total = cur;
 }
 
@@ -175,7 +174,7 @@ extern "C" int sharp_plan_create(sharp_plan* out, int nx, int ny, int m, int K, 
             if (r != 0) return SHARP_ERR_INVALID_ARG;
         if (o.periodic < 0 || o.periodic > 1 || o.probe_every < 0 || o.probe_start < 0 || !(o.eps_D >= 0.f) ||
             !(o.tile == 0 || o.tile == 16 || o.tile == 32 || o.tile == 64) || o.merge_split < 0 ||
-            o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 2 ||
+            o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 1 ||
             !(o.fft_block == 0 || o.fft_block == 128 || o.fft_block == 256 || o.fft_block == 512))
             return SHARP_ERR_INVALID_ARG;
     }
@@ -244,17 +243,6 @@ extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
         HIPCHK(hipMemcpyAsync(p->ws + p->off.tile_frames, p->tile_frames.data(),
                               p->tile_frames.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(launch_fill(p->ws + p->off.flag, 16 * sizeof(int), s));
-    if (p->m == 256) {
-        int dev = 0, cus = 0, xcc = 0;
-        HIPCHK(hipGetDevice(&dev));
-        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || xcc < 1 || xcc > 16)
-            xcc = 0;
-        (void)hipGetLastError();
-        p->xf_nq = xcc;
-        p->xf_grid = xcc ? xf_blocks_per_cu() * cus : 0;
-        if (!p->xf_nq && p->frame_launch == 2) p->frame_launch = 1;
-    }
     HIPCHK(launch_fill(p->ws + p->off.hist, kHistCap * sizeof(float), s));
     // host vectors are locals: finish the uploads before returning
     HIPCHK(hipStreamSynchronize(s));
@@ -319,7 +307,7 @@ int sharp::resid_blocks_default(const sharp_plan_s& p) {
 }
 
 int sharp::resid_blocks(const sharp_plan_s& p) {
-    if (p.m == 256 && p.frame_launch == 1) return p.K * (4096 / p.fft_block);
+    if (p.m == 256) return p.K * (4096 / p.fft_block);
     return resid_blocks_default(p);
 }
 
@@ -403,10 +391,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     A.beta = beta;
     int blocks = 0;
     const Timer* t = p.tm();
-    if (p.m == 256 && p.frame_launch == 2) {
-        HIPCHK(launch_xf_256(A, p.at<int>(p.off.xsync), p.at<int>(p.off.flag), p.xf_nq, p.xf_grid, s, t));
-        blocks = p.K * 16;
-    } else if (p.m == 256) {
+    if (p.m == 256) {
         HIPCHK(launch_raar_mp256(A, p.fft_block, s, t, &blocks));
     } else {
         HIPCHK(launch_frame(FM_RAAR, A, 0, s, &blocks, t));

@@ -106,11 +106,6 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // m = 256 RAAR frame phase in three launches with a chosen pass block size
 hipError_t launch_raar_mp256(const FrameArgs& A, int threads, hipStream_t s, const Timer* t, int* blocks_used);
-// m = 256 frame phase in one persistent XCD-local launch (kernels_frame.hip)
-int xf_blocks_per_cu();
-hipError_t launch_xf_256(const FrameArgs& A, int* sync_base, int* flag, int nq, int grid, hipStream_t s,
-                         const Timer* t);
-
 // batched execution (kernels_frame.hip, kernels_merge.hip)
 constexpr int kMaxBatch = 256;
 struct EpsDesc {

@@ -212,49 +212,6 @@ def test_not_ready_errors():
         p.object()
 
 
-@pytest.mark.parametrize("periodic", [False, True])
-def test_persistent_large_frame_launch_matches_three_launches(periodic):
-    """The one-launch XCD-local frame phase for m = 256 runs the same per-item
-    arithmetic as the three-launch form, so both give identical iterates."""
-    from paper_1602_01448_amd import Plan
-    rng = np.random.default_rng(31)
-    n, m = (768, 256)
-    if periodic:
-        pos = np.array([(64 * j, 64 * k) for j in range(12) for k in range(12)], np.int32)
-    else:
-        pos = gen.raster_positions(11, 51.2, n, m, jitter=2, rng=rng)
-    obj = gen.random_object(rng, n, n)
-    probe = gen.fresnel_aperture_probe(m, 60.0, 10.0)
-    I = O.forward_intensity(obj, probe, pos, periodic).astype(np.float32)
-    psi0 = c64(rng.uniform(0, 1, (n, n)))
-    outs = []
-    for fl in (1, 2):
-        p = Plan(n, n, m, pos, periodic=periodic, frame_launch=fl)
-        p.set_data(to_dev(I)).set_probe(to_dev(c64(probe))).set_object(to_dev(psi0)).raar(4, 0.75)
-        p.sync()
-        outs.append((to_host(p.object()), p.metrics(), p.info()["frame_launch"]))
-    assert outs[0][2] == 1 and outs[1][2] == 2
-    assert np.array_equal(outs[0][0], outs[1][0])
-    assert np.array_equal(outs[0][1], outs[1][1])
-
-
-def test_persistent_large_frame_launch_full_size():
-    """Full 2025 x 256^2 scan: two iterations, one-launch form = three-launch form."""
-    from paper_1602_01448_amd import Plan
-    s = gen.config_scan(3)
-    outs = []
-    for fl in (1, 2):
-        p = Plan(s.n, s.n, s.m, s.positions, frame_launch=fl)
-        w = to_dev(c64(s.probe))
-        I = p.simulate(to_dev(c64(s.obj)), w)
-        p.set_data(I).set_probe(w).set_object(to_dev(c64(s.psi0))).raar(2, 0.75)
-        p.sync()
-        outs.append((to_host(p.object()), p.metrics()))
-        del p, I
-    assert np.array_equal(outs[0][0], outs[1][0])
-    assert np.array_equal(outs[0][1], outs[1][1])
-
-
 @pytest.mark.parametrize("block", [128, 256, 512])
 def test_large_frame_pass_block_sizes(block):
     """Every pass block size of the three-launch m = 256 form matches the oracle."""
