@@ -70,10 +70,12 @@ typedef struct sharp_options {
     int tile;         /* merge tile side in object pixels: 16, 32 or 64 (0 = tuned) */
     int merge_split;  /* frame chunks per tile in the first merge pass, >= 1 (0 = tuned) */
     int grad_groups;  /* workgroups of the gradient frame kernel (0 = tuned) */
-    int frame_launch; /* m = 256 RAAR frame phase: 0 or 1 = three launches (row, column,
-                         row passes); other values are rejected (reserved) */
-    int fft_block;    /* m = 256, three-launch form: threads per pass workgroup, 128, 256 or
-                         512 (8, 16 or 32 rows / columns per workgroup); 0 = tuned */
+    int frame_launch; /* m = 256 RAAR: 0 = default (2 when the object is at most 8192
+                         wide, else 1); 1 = row, column and row passes with the carry in
+                         frame space, then the tile merge; 2 = carry kept in the Fourier
+                         domain, merge fused into the last (inverse row) pass */
+    int fft_block;    /* m = 256, form 1: threads per pass workgroup, 128, 256 or 512 (8, 16
+                         or 32 rows / columns per workgroup); 0 = 256 */
     int reserved[3];  /* must be zero */
 } sharp_options;
 

@@ -4,9 +4,10 @@ Times candidate launch configurations of the library on the GPU and keeps the
 fastest per geometry:
 
 * merge tile side (16, 32, 64) and frame-chunk split of the overlap merge;
-* for 256 x 256 frames, the pass workgroup size of the three-pass frame
-  phase (128, 256 or 512 threads, i.e. 8, 16 or 32 rows / columns of a
-  frame per workgroup);
+* for 256 x 256 frames, the form of the iteration (Fourier-domain carry with
+  the merge fused into the last pass, or frame-space carry with a separate
+  merge) and, for the latter, the pass workgroup size (128, 256 or 512
+  threads, i.e. 8, 16 or 32 rows / columns of a frame per workgroup);
 * the workgroup count of the gradient frame kernel.
 
 Candidates are timed with HIP events over a few RAAR iterations (or gradient
@@ -80,7 +81,7 @@ def _merge_candidates(n: int):
 def _frame_candidates(m: int):
     if m != 256:
         return [{}]
-    return [{"fft_block": b} for b in (128, 256, 512)]
+    return [{"frame_launch": 2}] + [{"frame_launch": 1, "fft_block": b} for b in (128, 256, 512)]
 
 
 def _synthetic(plan: Plan, seed: int):
@@ -145,7 +146,7 @@ def tune_raar(nx: int, ny: int, m: int, positions, periodic: bool = False, iters
             best_merge, best_t = mc, t
         del p
     best = dict(best_merge)
-    for fc in [c for c in _frame_candidates(m) if c and c.get("fft_block") != 256]:
+    for fc in [c for c in _frame_candidates(m) if c and c.get("frame_launch") != 2]:
         opts = {**best_merge, **fc}
         p = Plan(nx, ny, m, positions, periodic=periodic, **opts)
         t = _time_raar(p, iters, reps)

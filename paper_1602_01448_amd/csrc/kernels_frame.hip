@@ -132,6 +132,12 @@ __device__ __forceinline__ void prologue2(const FrameArgs& A, int frame, int y, 
         z1 = cadd(z1, cscale(cmul(w1, p1), A.g));
     } else if constexpr (MODE == FM_PA || MODE == FM_F || MODE == FM_FINV) {
         ld2(A.in + fb, off, z0, z1);
+    } else if constexpr (MODE == FM_GATHER) {
+        float2 p0, p1, w0, w1;
+        gather2(A, frame, y, x, p0, p1);
+        ld2(A.w_g, pix, w0, w1);
+        z0 = cscale(cmul(w0, p0), A.g);
+        z1 = cscale(cmul(w1, p1), A.g);
     } else {  // GRAD, SIM, Q
         float2 w0, w1;
         gather2(A, frame, y, x, t0, t1);
@@ -298,12 +304,15 @@ __device__ __forceinline__ void fg_group(const FrameArgs& A, int grp, float2* ld
         } else if constexpr (MODE == FM_PA) {
             st2(A.out + fb, e0, y0, y1);
         } else if constexpr (MODE == FM_GRAD) {
-            float2 w0, w1;
+            // T psi is gathered again (object reads hit the caches) rather than
+            // held in registers across the transforms
+            float2 w0, w1, t0, t1;
             ld2(A.w, rem, w0, w1);
+            gather2(A, frame, rem / M, rem % M, t0, t1);
             const float2 r0 = cscale(y0, 2.f), r1 = cscale(y1, 2.f);
             st2(A.v + fb, e0, cconjmul(w0, r0), cconjmul(w1, r1));
-            gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t[2 * k], r0));
-            gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t[2 * k + 1], r1));
+            gacc[2 * k] = cadd(gacc[2 * k], cconjmul(t0, r0));
+            gacc[2 * k + 1] = cadd(gacc[2 * k + 1], cconjmul(t1, r1));
         }
     }
     __syncthreads();
@@ -395,10 +404,12 @@ __global__ void __launch_bounds__(NTB) mp_row_fwd(FrameArgs A) {
 
 template <int M, int MODE, int NTB = 256>
 struct CBPost {
-    ModOp<MODE, M> op;  // bases point at the frame's column block
+    ModOp<MODE, M> op;  // bases point at the frame (amplitudes: column-block layout)
+    int x0;             // first column of this block
     __device__ __forceinline__ void operator()(int addr, float2& v) {
         constexpr int CB = MP<M, NTB>::CB;
-        op.apply(true, (unsigned)((addr / CB) * M + addr % CB), v);
+        const unsigned y = addr / CB, x = x0 + addr % CB;
+        op.apply(true, MODE == FM_SIM ? y * M + x : cb256(y, x), v);
     }
 };
 
@@ -422,7 +433,7 @@ __device__ __forceinline__ float mp_col_item(const FrameArgs& A, int it, float2*
     }
     __syncthreads();
     constexpr int D1 = (MODE == FM_FINV) ? -1 : 1;
-    CBPost<M, MODE, NTB> post{{A.a + fb + cb * CB, A.out_f + fb + cb * CB, 0.f}};
+    CBPost<M, MODE, NTB> post{{A.a + fb, A.out_f + fb, 0.f}, cb * CB};
     fft_1d_post<M, D1, NT, CB, ColLayCB<CB>>(lds, twl, post);
     if constexpr (MODE == FM_SIM) return post.op.resid;
     float2* dst = A.stage;
@@ -862,6 +873,328 @@ hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* 
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// m = 256 with the RAAR carry kept in the Fourier domain.
+//
+// With U = F u the iterate's spectrum is Z = U + F(g w_g T psi_v), so the
+// row pass only transforms the gathered object term, the column pass forms
+// Z, the projection Y = a sgn Z, the new carry U' = b Z + (1 - 2b) Y and the
+// spectrum of the merge input V = 2Y - Z (then inverse column FFTs), and the
+// last pass inverse-transforms rows of V straight into the overlap merge.
+// The carry and the amplitudes are stored column-block-major (cb256), so the
+// column pass reads and writes one contiguous block per workgroup.
+// ---------------------------------------------------------------------------
+__device__ float col_carry_item(const FrameArgs& A, int it, float2* lds, const float2* twl) {
+    const int tid = opaque_tid();
+    constexpr int M = 256;
+    using C = MP<M, 256>;
+    constexpr int NT = C::NT, NP = C::NP, CB = C::CB, MM = M * M, NCB = C::NCB;
+    static_assert(CB == 16, "column block must match the cb256 layout");
+    const int frame = it / NCB, cb = it % NCB;
+    const size_t fb = (size_t)frame * MM;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (tid + NT * k);
+        const int y = e0 / CB, c = e0 % CB;
+        float2 a0, a1;
+        ld2(A.stage + fb, y * M + cb * CB + c, a0, a1);
+        lds[pidx(e0)] = a0;
+        lds[pidx(e0 + 1)] = a1;
+    }
+    __syncthreads();
+    NoPost none;
+    fft_1d<M, 1, NT, CB, ColLayCB<CB>>(lds, twl, none);
+    // pointwise in the Fourier domain; LDS element e0 = y * 16 + c is also the
+    // offset of (y, 16 cb + c) inside this block of the cb256 layout
+    const size_t blk = fb + (size_t)cb * M * CB;
+    const float inv_m = 1.0f / M, b = A.beta, c1 = 1.f - 2.f * A.beta;
+    ModOp<FM_RAAR, M> op{nullptr, nullptr, 0.f};
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (tid + NT * k);
+        float2 u0, u1;
+        ld2(A.u + blk, e0, u0, u1);
+        const float2 av = ldf2(A.a + blk, e0);
+        const float2 z0 = cadd(u0, cscale(lds[pidx(e0)], inv_m));
+        const float2 z1 = cadd(u1, cscale(lds[pidx(e0 + 1)], inv_m));
+        const float2 y0 = op.modulus(z0, av.x, true), y1 = op.modulus(z1, av.y, true);
+        st2(A.u + blk, e0, cadd(cscale(z0, b), cscale(y0, c1)), cadd(cscale(z1, b), cscale(y1, c1)));
+        lds[pidx(e0)] = csub(cscale(y0, 2.f), z0);
+        lds[pidx(e0 + 1)] = csub(cscale(y1, 2.f), z1);
+    }
+    __syncthreads();
+    fft_1d<M, -1, NT, CB, ColLayCB<CB>>(lds, twl, none);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (tid + NT * k);
+        const int y = e0 / CB, c = e0 % CB;
+        st2(A.stage + fb, y * M + cb * CB + c, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+    }
+    __syncthreads();
+    return op.resid;
+}
+
+__global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
+    using C = MP<256, 256>;
+    extern __shared__ float2 smem[];
+    __shared__ float red[C::NT / 64];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    for (int t = threadIdx.x; t < 256; t += C::NT) twl[t] = A.tw[t];
+    const int items = A.K * C::NCB;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const float s = block_sum(col_carry_item(A, it, lds, twl), red);
+        if (threadIdx.x == 0) A.resid[it] = s;
+    }
+}
+
+// Inverse row FFTs of the frame rows that land in object strip s (SH rows),
+// multiplied by conj(w) and summed in ascending frame order into the strip,
+// then psi_v = D^+ * sum.  A thread owns object columns t, t + 256, ... of the
+// strip, so the per-pixel order of the sum is the frame order and no two
+// threads touch one pixel.
+
+__device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int strip, float2* lds, const float2* twl,
+                                 float2* acc) {
+    constexpr int M = 256, NT = 256, NP = 8, LINES = 16, MM = M * M;
+    const int tid = opaque_tid();
+    const int SH = S.SH, FPB = LINES / SH, nx = A.nx, ny = A.ny;
+    const int y0 = strip * SH;
+    for (int i = tid; i < SH * nx; i += NT) acc[i] = make_float2(0.f, 0.f);
+    const int b = S.ptr[strip], e = S.ptr[strip + 1];
+    const float inv_m = 1.0f / M;
+    for (int i = b; i < e; i += FPB) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (tid + NT * k);
+            const int line = e0 / M, x = e0 % M, fk = line / SH, sr = line % SH;
+            float2 v0 = make_float2(0.f, 0.f), v1 = v0;
+            if (i + fk < e) {
+                const int f = S.frames[i + fk];
+                int r = y0 + sr - A.pos[2 * f];
+                if (A.periodic && r < 0) r += ny;
+                if ((unsigned)r < (unsigned)M && y0 + sr < ny) ld2(A.stage + (size_t)f * MM, r * M + x, v0, v1);
+            }
+            lds[pidx(e0)] = v0;
+            lds[pidx(e0 + 1)] = v1;
+        }
+        __syncthreads();
+        NoPost none;
+        fft_1d<M, -1, NT, LINES, RowLay<M>>(lds, twl, none);
+        for (int fk = 0; fk < FPB && i + fk < e; ++fk) {
+            const int f = S.frames[i + fk];
+            const int py = A.pos[2 * f], px = A.pos[2 * f + 1];
+            for (int sr = 0; sr < SH; ++sr) {
+                int r = y0 + sr - py;
+                if (A.periodic && r < 0) r += ny;
+                if ((unsigned)r >= (unsigned)M || y0 + sr >= ny) continue;
+                for (int gx = tid; gx < nx; gx += NT) {
+                    int x = gx - px;
+                    if (A.periodic && x < 0) x += nx;
+                    if ((unsigned)x >= (unsigned)M) continue;
+                    const float2 yv = cscale(lds[pidx((fk * SH + sr) * M + x)], inv_m);
+                    const float2 wv = ldc(A.w, (unsigned)(r * M + x));
+                    float2& a = acc[sr * nx + gx];
+                    a = cadd(a, cconjmul(wv, yv));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int sr = 0; sr < SH; ++sr) {
+        const int y = y0 + sr;
+        if (y >= ny) break;
+        for (int gx = tid; gx < nx; gx += NT) {
+            const unsigned o = (unsigned)y * (unsigned)nx + gx;
+            S.out[o] = cscale(acc[sr * nx + gx], S.Dinv[o]);
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) strip_merge_kernel(FrameArgs A, StripArgs S) {
+    extern __shared__ float2 smem[];
+    float2* lds = smem;
+    float2* twl = smem + pidx(16 * 256);
+    float2* acc = twl + 256;
+    for (int t = threadIdx.x; t < 256; t += 256) twl[t] = A.tw[t];
+    __syncthreads();
+    strip_merge_item(A, S, blockIdx.x, lds, twl, acc);
+}
+
+// Batched form: phase 0 gather + row FFTs, 1 column pass with the carry,
+// 2 strip merge; items (scan, local item), identical arithmetic.
+template <int PHASE>
+__global__ void __launch_bounds__(256) batch_carry_kernel(const FrameArgs* __restrict__ D,
+                                                          const StripArgs* __restrict__ SD,
+                                                          const int2* __restrict__ items, int n) {
+    using C = MP<256, 256>;
+    extern __shared__ float2 smem[];
+    __shared__ float red[4];
+    float2* lds = smem;
+    float2* twl = smem + (PHASE == 2 ? pidx(16 * 256) : C::LDS);
+    if (n <= 0) return;
+    const float2* tw = D[items[0].x].tw;
+    for (int t = threadIdx.x; t < 256; t += 256) twl[t] = tw[t];
+    __syncthreads();
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        const FrameArgs A = D[w.x];
+        if constexpr (PHASE == 0) {
+            mp_row_fwd_item<256, FM_GATHER, 256>(A, w.y, lds, twl);
+        } else if constexpr (PHASE == 1) {
+            const float s = block_sum(col_carry_item(A, w.y, lds, twl), red);
+            if (threadIdx.x == 0) A.resid[w.y] = s;
+        } else {
+            strip_merge_item(A, SD[w.x], w.y, lds, twl, twl + 256);
+        }
+    }
+}
+
+size_t carry_phase_smem() { return MP<256, 256>::SMEM; }
+
+hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu) {
+    hipError_t e = hipSuccess;
+    int nb = 0;
+    if (phase == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_carry_kernel<0>, 256, smem);
+    else if (phase == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_carry_kernel<1>, 256, smem);
+    else {
+        e = hipFuncSetAttribute((const void*)batch_carry_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_carry_kernel<2>, 256, smem);
+    }
+    *blocks_per_cu = nb > 0 ? nb : 1;
+    return e;
+}
+
+hipError_t launch_batch_carry(int phase, const FrameArgs* D, const StripArgs* SD, const int2* items, int n, int grid,
+                              size_t smem, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (phase == 0) hipLaunchKernelGGL(batch_carry_kernel<0>, dim3(grid), dim3(256), smem, s, D, SD, items, n);
+    else if (phase == 1) hipLaunchKernelGGL(batch_carry_kernel<1>, dim3(grid), dim3(256), smem, s, D, SD, items, n);
+    else hipLaunchKernelGGL(batch_carry_kernel<2>, dim3(grid), dim3(256), smem, s, D, SD, items, n);
+    return hipGetLastError();
+}
+
+// Carry <-> space: u = F* U (column pass then row pass) and U = F u.
+__global__ void __launch_bounds__(256) carry_cols_kernel(FrameArgs A, int dir) {
+    using C = MP<256, 256>;
+    constexpr int M = 256, NT = C::NT, NP = C::NP, CB = C::CB, MM = M * M, NCB = C::NCB;
+    extern __shared__ float2 smem[];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
+    const int items = A.K * NCB;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int tid = opaque_tid();
+        const int frame = it / NCB, cb = it % NCB;
+        const size_t fb = (size_t)frame * MM, blk = fb + (size_t)cb * M * CB;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (tid + NT * k);
+            const int y = e0 / CB, c = e0 % CB;
+            float2 a0, a1;
+            if (dir < 0) ld2(A.in + blk, e0, a0, a1);                    // carry block
+            else ld2(A.stage + fb, y * M + cb * CB + c, a0, a1);         // row-transformed frame
+            lds[pidx(e0)] = a0;
+            lds[pidx(e0 + 1)] = a1;
+        }
+        __syncthreads();
+        NoPost none;
+        if (dir < 0) fft_1d<M, -1, NT, CB, ColLayCB<CB>>(lds, twl, none);
+        else fft_1d<M, 1, NT, CB, ColLayCB<CB>>(lds, twl, none);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (tid + NT * k);
+            const int y = e0 / CB, c = e0 % CB;
+            const float2 v0 = lds[pidx(e0)], v1 = lds[pidx(e0 + 1)];
+            if (dir < 0) st2(A.stage + fb, y * M + cb * CB + c, v0, v1);
+            else st2(A.out + blk, e0, cscale(v0, 1.0f / M), cscale(v1, 1.0f / M));
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) carry_rows_inv_kernel(FrameArgs A) {
+    using C = MP<256, 256>;
+    constexpr int M = 256, NT = C::NT, NP = C::NP, RB = C::RB, MM = M * M, NRB = C::NRB;
+    extern __shared__ float2 smem[];
+    float2* lds = smem;
+    float2* twl = smem + C::LDS;
+    for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
+    const int items = A.K * NRB;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int tid = opaque_tid();
+        const int frame = it / NRB, rb = it % NRB;
+        const size_t fb = (size_t)frame * MM;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (tid + NT * k);
+            float2 a0, a1;
+            ld2(A.stage + fb, rb * RB * M + e0, a0, a1);
+            lds[pidx(e0)] = a0;
+            lds[pidx(e0 + 1)] = a1;
+        }
+        __syncthreads();
+        NoPost none;
+        fft_1d<M, -1, NT, RB, RowLay<M>>(lds, twl, none);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int e0 = 2 * (tid + NT * k);
+            st2(A.out + fb, rb * RB * M + e0, cscale(lds[pidx(e0)], 1.0f / M), cscale(lds[pidx(e0 + 1)], 1.0f / M));
+        }
+        __syncthreads();
+    }
+}
+
+size_t strip_smem_bytes(int SH, int nx) {
+    return (size_t)(pidx(16 * 256) + 256 + SH * nx) * sizeof(float2);
+}
+
+hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int* strip_frames, int SH,
+                                 int nstrips, const float* Dinv, float2* psi_out, hipStream_t s, const Timer* tp,
+                                 int* blocks_used) {
+    const Timer& t = tp ? *tp : kNoTimer;
+    using C = MP<256, 256>;
+    const int rows = A.K * C::NRB, cols = A.K * C::NCB;
+    t.begin(TC_FRAME);
+    hipLaunchKernelGGL((mp_row_fwd<256, FM_GATHER, 256>), dim3(rows), dim3(256), C::SMEM, s, A);
+    t.end(TC_FRAME);
+    t.begin(TC_COLS);
+    hipLaunchKernelGGL(col_carry_kernel, dim3(cols), dim3(256), C::SMEM, s, A);
+    t.end(TC_COLS);
+    *blocks_used = cols;
+    static bool attr = false;
+    const size_t smem = strip_smem_bytes(SH, A.nx);
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)strip_merge_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    StripArgs S{strip_ptr, strip_frames, Dinv, psi_out, SH};
+    t.begin(TC_MERGE);
+    hipLaunchKernelGGL(strip_merge_kernel, dim3(nstrips), dim3(256), smem, s, A, S);
+    t.end(TC_MERGE);
+    return hipGetLastError();
+}
+
+// u = F* U for the K frames of A.in (carry blocks) into A.out (natural layout)
+hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s) {
+    using C = MP<256, 256>;
+    hipLaunchKernelGGL(carry_cols_kernel, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A, -1);
+    hipLaunchKernelGGL(carry_rows_inv_kernel, dim3(A.K * C::NRB), dim3(256), C::SMEM, s, A);
+    return hipGetLastError();
+}
+
+// U = F u for the K frames of A.in (natural layout) into A.out (carry blocks)
+hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s) {
+    using C = MP<256, 256>;
+    hipLaunchKernelGGL((mp_row_fwd<256, FM_F, 256>), dim3(A.K * C::NRB), dim3(256), C::SMEM, s, A);
+    hipLaunchKernelGGL(carry_cols_kernel, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A, 1);
     return hipGetLastError();
 }
 

@@ -212,7 +212,8 @@ __device__ __forceinline__ float block_sum256(float x, float* red) {
 }
 
 __global__ void __launch_bounds__(256) set_data_kernel(const float* __restrict__ I, float* __restrict__ a, size_t n,
-                                                       float* __restrict__ partials, int* __restrict__ flag) {
+                                                       float* __restrict__ partials, int* __restrict__ flag,
+                                                       int blocked256) {
     __shared__ float red[4];
     float s = 0.f;
     bool bad = false;
@@ -220,7 +221,12 @@ __global__ void __launch_bounds__(256) set_data_kernel(const float* __restrict__
         const float v = I[i];
         bad |= !isfinite(v);
         const float r = sqrtf(fmaxf(v, 0.f));
-        a[i] = r;
+        size_t o = i;
+        if (blocked256) {
+            const unsigned p = (unsigned)(i & 65535u);
+            o = (i - p) + cb256(p >> 8, p & 255u);
+        }
+        a[o] = r;
         s += r * r;
     }
     if (bad) flag[0] = 1;
@@ -277,9 +283,10 @@ __global__ void __launch_bounds__(256) mean_amp_kernel(const float* __restrict__
                                                        float2* __restrict__ out) {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= MM) return;
+    const unsigned ap = (MM == 65536) ? cb256(p >> 8, p & 255) : (unsigned)p;  // m = 256: column-block layout
     float s = 0.f;
     for (int f = 0; f < K; ++f) {
-        const float v = a[(size_t)f * MM + p];
+        const float v = a[(size_t)f * MM + ap];
         s += v * v;
     }
     out[p] = make_float2(sqrtf(s / K), 0.f);
@@ -303,9 +310,9 @@ __global__ void __launch_bounds__(256) fill_kernel(uint4* __restrict__ p, size_t
 }
 
 hipError_t launch_set_data(const float* I, float* a, size_t n, float* partials, int* flag, hipStream_t s,
-                           int* blocks_used) {
+                           int* blocks_used, int blocked256) {
     const int grid = (int)std::min<size_t>(std::max<size_t>((n + 255) / 256, 1), 2048);
-    hipLaunchKernelGGL(set_data_kernel, dim3(grid), dim3(256), 0, s, I, a, n, partials, flag);
+    hipLaunchKernelGGL(set_data_kernel, dim3(grid), dim3(256), 0, s, I, a, n, partials, flag, blocked256);
     *blocks_used = grid;
     return hipGetLastError();
 }

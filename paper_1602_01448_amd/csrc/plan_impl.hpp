@@ -22,7 +22,7 @@ inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
 
 struct Offsets {
     size_t tw, pos, tile_ptr, tile_frames, a, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
-    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, total;
+    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sfr, total;
 };
 
 }  // namespace sharp
@@ -32,7 +32,9 @@ struct sharp_plan_s {
     sharp_options opt{};
     std::vector<int32_t> pos;
     int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
-    int frame_launch = 1;     // m = 256: 1 = three launches (the only form)
+    int frame_launch = 1;     // m = 256: 1 = three passes + tile merge; 2 = Fourier carry + strip merge
+    int SH = 0, nstrips = 0;  // strip merge: object rows per strip (0 = form unavailable)
+    std::vector<int32_t> strip_ptr, strip_frames;
     int fft_block = 256;      // m = 256, three launches: threads per pass workgroup
     std::vector<int32_t> tile_ptr, tile_frames;
     sharp::Offsets off{};
@@ -63,6 +65,7 @@ struct sharp_plan_s {
     const sharp::Timer* tm() const { return timing ? &timer : nullptr; }
 
     template <class T> T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+    bool carry_form() const { return m == 256 && frame_launch == 2; }
     size_t frame_elems() const { return (size_t)K * m * m; }
     size_t obj_elems() const { return (size_t)nx * ny; }
 };

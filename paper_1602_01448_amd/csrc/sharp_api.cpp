@@ -96,6 +96,34 @@ static void build_csr(sharp_plan_s& p) {
     }
 }
 
+// Frames touching each strip of SH object rows, ascending (strip merge).
+static void build_strips(sharp_plan_s& p) {
+    p.nstrips = (p.ny + p.SH - 1) / p.SH;
+    std::vector<int> count(p.nstrips, 0), hit;
+    auto strips_of = [&](int i, std::vector<int>& out) {
+        out.clear();
+        const int py = p.pos[2 * i];
+        for (int r = 0; r < p.m; ++r) {
+            int y = py + r;
+            if (y >= p.ny) y -= p.ny;  // periodic only
+            const int sidx = y / p.SH;
+            if (std::find(out.begin(), out.end(), sidx) == out.end()) out.push_back(sidx);
+        }
+    };
+    for (int i = 0; i < p.K; ++i) {
+        strips_of(i, hit);
+        for (int sidx : hit) ++count[sidx];
+    }
+    p.strip_ptr.assign(p.nstrips + 1, 0);
+    for (int t = 0; t < p.nstrips; ++t) p.strip_ptr[t + 1] = p.strip_ptr[t] + count[t];
+    p.strip_frames.assign(p.strip_ptr[p.nstrips], 0);
+    std::vector<int> fill(p.strip_ptr.begin(), p.strip_ptr.end() - 1);
+    for (int i = 0; i < p.K; ++i) {
+        strips_of(i, hit);
+        for (int sidx : hit) p.strip_frames[fill[sidx]++] = i;
+    }
+}
+
 static void choose_tuning(sharp_plan_s& p) {
     // tile side: small objects use small tiles so that enough workgroups exist
     if (p.opt.tile) p.T = p.opt.tile;
@@ -115,8 +143,14 @@ static void choose_tuning(sharp_plan_s& p) {
     else p.grad_groups = (p.m == 256) ? 1024 : std::min(groups, p.m == 128 ? 256 : 512);
     if (p.m == 256) p.grad_groups = std::max(16, p.grad_groups / 16 * 16);
     p.probe_chunks = std::min(p.K, 128);
-    p.frame_launch = p.opt.frame_launch ? p.opt.frame_launch : 1;
     p.fft_block = p.opt.fft_block ? p.opt.fft_block : 256;
+    // m = 256: Fourier-domain carry with the merge fused into the last row pass
+    // unless asked otherwise; needs a strip of the object in LDS
+    p.SH = p.m != 256 ? 0 : p.nx <= 4096 ? 2 : p.nx <= 8192 ? 1 : 0;
+    p.frame_launch = p.opt.frame_launch ? p.opt.frame_launch : (p.m == 256 ? 2 : 1);
+    if (p.frame_launch == 2 && !p.SH) p.frame_launch = 1;
+    if (p.m != 256) p.frame_launch = 1;
+    if (p.carry_form()) build_strips(p);
 }
 
 static void layout(sharp_plan_s& p) {
@@ -156,6 +190,8 @@ static void layout(sharp_plan_s& p) {
     o.hist = take(kHistCap * sizeof(float));
     o.scal = take(16 * sizeof(float));
     o.flag = take(16 * sizeof(int));
+    o.sptr = take((p.strip_ptr.size() + 1) * sizeof(int32_t));
+    o.sfr = take((p.strip_frames.size() + 1) * sizeof(int32_t));
     o.total = cur;
 }
 
@@ -174,7 +210,7 @@ extern "C" int sharp_plan_create(sharp_plan* out, int nx, int ny, int m, int K, 
             if (r != 0) return SHARP_ERR_INVALID_ARG;
         if (o.periodic < 0 || o.periodic > 1 || o.probe_every < 0 || o.probe_start < 0 || !(o.eps_D >= 0.f) ||
             !(o.tile == 0 || o.tile == 16 || o.tile == 32 || o.tile == 64) || o.merge_split < 0 ||
-            o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 1 ||
+            o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 2 ||
             !(o.fft_block == 0 || o.fft_block == 128 || o.fft_block == 256 || o.fft_block == 512))
             return SHARP_ERR_INVALID_ARG;
     }
@@ -243,6 +279,12 @@ extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
         HIPCHK(hipMemcpyAsync(p->ws + p->off.tile_frames, p->tile_frames.data(),
                               p->tile_frames.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(launch_fill(p->ws + p->off.flag, 16 * sizeof(int), s));
+    if (!p->strip_ptr.empty()) {
+        HIPCHK(hipMemcpyAsync(p->ws + p->off.sptr, p->strip_ptr.data(), p->strip_ptr.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(p->ws + p->off.sfr, p->strip_frames.data(), p->strip_frames.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+    }
     HIPCHK(launch_fill(p->ws + p->off.hist, kHistCap * sizeof(float), s));
     // host vectors are locals: finish the uploads before returning
     HIPCHK(hipStreamSynchronize(s));
@@ -307,7 +349,7 @@ int sharp::resid_blocks_default(const sharp_plan_s& p) {
 }
 
 int sharp::resid_blocks(const sharp_plan_s& p) {
-    if (p.m == 256) return p.K * (4096 / p.fft_block);
+    if (p.m == 256 && !p.carry_form()) return p.K * (4096 / p.fft_block);
     return resid_blocks_default(p);
 }
 
@@ -325,7 +367,7 @@ extern "C" int sharp_set_data(sharp_plan p, const float* d_I) {
     if (!p->has_ws) return SHARP_ERR_NOT_READY;
     int blocks = 0;
     HIPCHK(launch_set_data(d_I, p->at<float>(p->off.a), p->frame_elems(), p->at<float>(p->off.resid),
-                           p->at<int>(p->off.flag), p->stream, &blocks));
+                           p->at<int>(p->off.flag), p->stream, &blocks, p->m == 256));
     HIPCHK(launch_reduce(p->at<float>(p->off.resid), blocks, p->at<float>(p->off.scal), p->stream));
     p->has_data = true;
     return SHARP_OK;
@@ -382,6 +424,13 @@ extern "C" int sharp_set_object(sharp_plan p, const void* d_psi) {
 // ---------------------------------------------------------------------------
 // iteration
 // ---------------------------------------------------------------------------
+// Fourier-domain carry (m = 256 merged form) -> frame space, into dst [K][m][m]
+static hipError_t carry_to_space(sharp_plan_s& p, float2* dst) {
+    FrameArgs A = frame_args(p);
+    A.in = p.at<float2>(p.off.u);
+    A.out = dst;
+    return launch_carry_to_space(A, p.stream);
+}
 static int one_iteration(sharp_plan_s& p, float beta) {
     hipStream_t s = p.stream;
     const long long it = p.iter + 1;
@@ -391,7 +440,11 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     A.beta = beta;
     int blocks = 0;
     const Timer* t = p.tm();
-    if (p.m == 256) {
+    if (p.carry_form()) {
+        // frame phase and merge in one sequence; psi_v is final afterwards
+        HIPCHK(launch_carry_raar_256(A, p.at<int>(p.off.sptr), p.at<int>(p.off.sfr), p.SH, p.nstrips,
+                                     p.at<float>(p.off.Dinv), p.at<float2>(p.off.psi_v), s, t, &blocks));
+    } else if (p.m == 256) {
         HIPCHK(launch_raar_mp256(A, p.fft_block, s, t, &blocks));
     } else {
         HIPCHK(launch_frame(FM_RAAR, A, 0, s, &blocks, t));
@@ -407,12 +460,26 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     p.hist_count++;
     p.g = beta;
     MergeArgs Mg = merge_args(p);
-    if (t) t->begin(TC_MERGE);
-    HIPCHK(launch_merge(probe_due ? MK_VU : MK_V, Mg, p.ntiles, s));
-    if (t) t->end(TC_MERGE);
+    const float2* u_space = p.at<float2>(p.off.u);
+    if (p.carry_form()) {
+        if (probe_due) {
+            // psi^(l) and the probe update need the carry in frame space
+            if (t) t->begin(TC_PROBE);
+            HIPCHK(carry_to_space(p, p.at<float2>(p.off.v)));
+            Mg.u = p.at<float2>(p.off.v);
+            Mg.out = p.at<float2>(p.off.psi_l);
+            HIPCHK(launch_merge(MK_U, Mg, p.ntiles, s));
+            u_space = p.at<float2>(p.off.v);
+            if (t) t->end(TC_PROBE);
+        }
+    } else {
+        if (t) t->begin(TC_MERGE);
+        HIPCHK(launch_merge(probe_due ? MK_VU : MK_V, Mg, p.ntiles, s));
+        if (t) t->end(TC_MERGE);
+    }
     if (probe_due) {
         if (t) t->begin(TC_PROBE);
-        HIPCHK(launch_probe_partial(p.m, p.K, p.at<int>(p.off.pos), p.nx, p.ny, p.opt.periodic, p.at<float2>(p.off.u),
+        HIPCHK(launch_probe_partial(p.m, p.K, p.at<int>(p.off.pos), p.nx, p.ny, p.opt.periodic, u_space,
                                     p.at<float2>(p.off.w_cur), p.at<float2>(p.off.psi_v), p.at<float2>(p.off.psi_l),
                                     beta, p.probe_chunks, p.at<float2>(p.off.pnum), p.at<float>(p.off.pden), s));
         HIPCHK(launch_probe_finish(p.m, p.probe_chunks, p.at<float2>(p.off.pnum), p.at<float>(p.off.pden),
@@ -449,6 +516,10 @@ extern "C" int sharp_get_object(sharp_plan p, void* d_out) {
     }
     MergeArgs A = merge_args(*p);
     A.out = (float2*)d_out;
+    if (p->carry_form()) {
+        HIPCHK(carry_to_space(*p, p->at<float2>(p->off.v)));
+        A.u = p->at<float2>(p->off.v);
+    }
     HIPCHK(launch_merge(MK_U, A, p->ntiles, p->stream));
     return SHARP_OK;
 }
@@ -613,7 +684,8 @@ extern "C" int sharp_get_state(sharp_plan p, void* d_state) {
     char* d = (char*)d_state;
     hipStream_t s = p->stream;
     const size_t MM = (size_t)p->m * p->m;
-    HIPCHK(launch_copy(d + L.u, p->ws + p->off.u, p->frame_elems() * sizeof(float2), s));
+    if (p->carry_form()) HIPCHK(carry_to_space(*p, (float2*)(d + L.u)));
+    else HIPCHK(launch_copy(d + L.u, p->ws + p->off.u, p->frame_elems() * sizeof(float2), s));
     HIPCHK(launch_copy(d + L.psi_v, p->ws + p->off.psi_v, p->obj_elems() * sizeof(float2), s));
     HIPCHK(launch_copy(d + L.psi_l, p->ws + p->off.psi_l, p->obj_elems() * sizeof(float2), s));
     HIPCHK(launch_copy(d + L.w_cur, p->ws + p->off.w_cur, MM * sizeof(float2), s));
@@ -638,7 +710,14 @@ extern "C" int sharp_set_state(sharp_plan p, const void* d_state) {
     if (h.magic != kMagic || h.nx != p->nx || h.ny != p->ny || h.m != p->m || h.K != p->K)
         return SHARP_ERR_INVALID_ARG;
     const size_t MM = (size_t)p->m * p->m;
-    HIPCHK(launch_copy(p->ws + p->off.u, d + L.u, p->frame_elems() * sizeof(float2), s));
+    if (p->carry_form()) {
+        FrameArgs A = frame_args(*p);
+        A.in = (const float2*)(d + L.u);
+        A.out = p->at<float2>(p->off.u);
+        HIPCHK(launch_space_to_carry(A, s));
+    } else {
+        HIPCHK(launch_copy(p->ws + p->off.u, d + L.u, p->frame_elems() * sizeof(float2), s));
+    }
     HIPCHK(launch_copy(p->ws + p->off.psi_v, d + L.psi_v, p->obj_elems() * sizeof(float2), s));
     HIPCHK(launch_copy(p->ws + p->off.psi_l, d + L.psi_l, p->obj_elems() * sizeof(float2), s));
     HIPCHK(launch_copy(p->ws + p->off.w_cur, d + L.w_cur, MM * sizeof(float2), s));

@@ -39,11 +39,13 @@ int t_class(int t) {
 
 struct sharp_batch_s {
     std::vector<sharp_plan_s*> plans;
-    std::vector<int2> frame_items[5];     // per frame-size class
+    std::vector<int2> frame_items[5];     // per frame-size class (m = 256: frame-space carry form)
     std::vector<int4> merge_items[3];     // per merge-tile class
     std::vector<int2> finish_items[3];
+    std::vector<int2> carry_items[3];     // m = 256 Fourier-carry form: rows, columns, strips
+    size_t carry_smem = 0;                // LDS of the strip phase (widest object)
     struct {
-        size_t fargs, margs, eps, fitems[5], mitems[3], fin[3], total;
+        size_t fargs, margs, eps, sargs, fitems[5], mitems[3], fin[3], citems[3], total;
     } off{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -51,6 +53,7 @@ struct sharp_batch_s {
     hipStream_t own = nullptr;       // batch stream (graphs are captured and replayed here)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int grid_frame[5][3] = {};
+    int grid_carry[3] = {};
     int grid_merge = 0;
     std::map<std::pair<int, float>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 
@@ -84,6 +87,15 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         for (int s = 0; s < nplans; ++s) {
             sharp_plan_s* p = plans[s];
             b->plans.push_back(p);
+            if (p->carry_form()) {
+                for (int it = 0; it < p->K * 16; ++it) {
+                    b->carry_items[0].push_back(make_int2(s, it));
+                    b->carry_items[1].push_back(make_int2(s, it));
+                }
+                for (int st = 0; st < p->nstrips; ++st) b->carry_items[2].push_back(make_int2(s, st));
+                b->carry_smem = std::max(b->carry_smem, strip_smem_bytes(p->SH, p->nx));
+                continue;  // merged in the strip phase, no tile merge
+            }
             const int mc = m_class(p->m);
             const int items = resid_blocks_default(*p);  // frame groups (m <= 128) or row blocks (m = 256)
             for (int it = 0; it < items; ++it) b->frame_items[mc].push_back(make_int2(s, it));
@@ -102,6 +114,8 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         b->off.fargs = take(nplans * sizeof(FrameArgs));
         b->off.margs = take(nplans * sizeof(MergeArgs));
         b->off.eps = take(nplans * sizeof(EpsDesc));
+        b->off.sargs = take(nplans * sizeof(StripArgs));
+        for (int c = 0; c < 3; ++c) b->off.citems[c] = take(b->carry_items[c].size() * sizeof(int2));
         for (int c = 0; c < 5; ++c) b->off.fitems[c] = take(b->frame_items[c].size() * sizeof(int2));
         for (int c = 0; c < 3; ++c) {
             b->off.mitems[c] = take(b->merge_items[c].size() * sizeof(int4));
@@ -149,10 +163,13 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
     std::vector<FrameArgs> fa(n);
     std::vector<MergeArgs> ma(n);
     std::vector<EpsDesc> ea(n);
+    std::vector<StripArgs> sa(n);
     for (int s = 0; s < n; ++s) {
         sharp_plan_s& p = *b->plans[s];
         fa[s] = frame_args(p);
         ma[s] = merge_args(p);
+        sa[s] = StripArgs{p.at<int>(p.off.sptr), p.at<int>(p.off.sfr), p.at<float>(p.off.Dinv),
+                          p.at<float2>(p.off.psi_v), p.SH};
         ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),
                         p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
     }
@@ -160,6 +177,11 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
     HIPCHK(hipMemcpyAsync(b->ws + b->off.fargs, fa.data(), n * sizeof(FrameArgs), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->ws + b->off.margs, ma.data(), n * sizeof(MergeArgs), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->ws + b->off.eps, ea.data(), n * sizeof(EpsDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->ws + b->off.sargs, sa.data(), n * sizeof(StripArgs), hipMemcpyHostToDevice, st));
+    for (int c = 0; c < 3; ++c)
+        if (!b->carry_items[c].empty())
+            HIPCHK(hipMemcpyAsync(b->ws + b->off.citems[c], b->carry_items[c].data(),
+                                  b->carry_items[c].size() * sizeof(int2), hipMemcpyHostToDevice, st));
     for (int c = 0; c < 5; ++c)
         if (!b->frame_items[c].empty())
             HIPCHK(hipMemcpyAsync(b->ws + b->off.fitems[c], b->frame_items[c].data(),
@@ -183,6 +205,12 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
             HIPCHK(batch_frame_prepare(kM[c], ph, &per));
             b->grid_frame[c][ph] = std::max(1, per * cus);
         }
+    for (int ph = 0; ph < 3; ++ph) {
+        int per = 1;
+        const size_t smem = ph == 2 ? b->carry_smem : carry_phase_smem();
+        if (!b->carry_items[ph].empty()) HIPCHK(batch_carry_prepare(ph, smem, &per));
+        b->grid_carry[ph] = std::max(1, per * cus);
+    }
     b->grid_merge = 8 * cus;
     return SHARP_OK;
 }
@@ -200,7 +228,19 @@ static int enqueue_iterations(sharp_batch_s& b, int n, float beta, hipStream_t s
             for (int ph = 0; ph < (kM[c] == 256 ? 3 : 1); ++ph)
                 HIPCHK(launch_batch_frame(kM[c], ph, D, items, cnt, std::min(cnt, b.grid_frame[c][ph]), s));
         }
+        for (int ph = 0; ph < 2; ++ph) {
+            const int cnt = (int)b.carry_items[ph].size();
+            if (cnt)
+                HIPCHK(launch_batch_carry(ph, D, b.at<StripArgs>(b.off.sargs), b.at<int2>(b.off.citems[ph]), cnt,
+                                          std::min(cnt, b.grid_carry[ph]), carry_phase_smem(), s));
+        }
         HIPCHK(launch_batch_eps(E, D, ns, beta, s));
+        {
+            const int cnt = (int)b.carry_items[2].size();
+            if (cnt)
+                HIPCHK(launch_batch_carry(2, D, b.at<StripArgs>(b.off.sargs), b.at<int2>(b.off.citems[2]), cnt,
+                                          std::min(cnt, b.grid_carry[2]), b.carry_smem, s));
+        }
         for (int c = 0; c < 3; ++c)
             HIPCHK(launch_batch_merge(kT[c], DM, b.at<int4>(b.off.mitems[c]), (int)b.merge_items[c].size(),
                                       b.at<int2>(b.off.fin[c]), (int)b.finish_items[c].size(), b.grid_merge, s));

@@ -19,7 +19,16 @@ enum FrameMode : int {
     FM_F = 4,     // in -> F in
     FM_FINV = 5,  // in -> F* in
     FM_Q = 6,     // psi -> w T psi
+    FM_GATHER = 7,  // z = g w_g T psi_v (Fourier-carry RAAR row pass, m = 256)
 };
+
+// For m = 256 the amplitudes (and the Fourier-domain carry) are stored
+// column-block-major: element (y, x) of a frame at ((x / 16) * 256 + y) * 16
+// + x % 16, so that a column-pass workgroup (16 columns) reads one
+// contiguous 32 KiB block.
+__host__ __device__ __forceinline__ unsigned cb256(unsigned y, unsigned x) {
+    return ((x >> 4) << 12) + (y << 4) + (x & 15u);
+}
 
 // Merge-kernel kinds
 enum MergeKind : int {
@@ -94,7 +103,7 @@ hipError_t launch_gw_finish(int M, int slots, const float2* part, float2* gw, hi
 // launchers (kernels_merge.hip)
 hipError_t launch_merge(int kind, const MergeArgs& a, int tiles, hipStream_t s);
 hipError_t launch_set_data(const float* I, float* a, size_t n, float* partials, int* flag,
-                           hipStream_t s, int* blocks_used);
+                           hipStream_t s, int* blocks_used, int blocked256);
 hipError_t launch_reduce(const float* partials, int n, float* out, hipStream_t s);
 hipError_t launch_eps(const float* partials, int n, const float* norm_a2, float* hist, int idx,
                       int* flag, hipStream_t s);
@@ -106,6 +115,26 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // m = 256 RAAR frame phase in three launches with a chosen pass block size
 hipError_t launch_raar_mp256(const FrameArgs& A, int threads, hipStream_t s, const Timer* t, int* blocks_used);
+// m = 256 RAAR with the carry in the Fourier domain and the merge fused into
+// the last row pass (kernels_frame.hip).  Strip merge arguments:
+struct StripArgs {
+    const int* __restrict__ ptr;     // [nstrips + 1]
+    const int* __restrict__ frames;  // frames touching each strip, ascending
+    const float* __restrict__ Dinv;
+    float2* __restrict__ out;        // psi_v
+    int SH;                          // object rows per strip
+};
+size_t carry_phase_smem();
+hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu);
+hipError_t launch_batch_carry(int phase, const FrameArgs* D, const StripArgs* SD, const int2* items, int n, int grid,
+                              size_t smem, hipStream_t s);
+size_t strip_smem_bytes(int SH, int nx);
+hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int* strip_frames, int SH,
+                                 int nstrips, const float* Dinv, float2* psi_out, hipStream_t s, const Timer* t,
+                                 int* blocks_used);
+hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s);
+hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s);
+
 // batched execution (kernels_frame.hip, kernels_merge.hip)
 constexpr int kMaxBatch = 256;
 struct EpsDesc {

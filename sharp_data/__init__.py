@@ -10,6 +10,7 @@ from .gen import (  # noqa: F401
     Scan,
     apply_poisson,
     config_scan,
+    fig3_scan,
     gradient_point,
     batch_scans,
     raster_positions,

@@ -191,6 +191,21 @@ def config_scan(cfg) -> Scan:
     raise ValueError(f"unknown workload {cfg!r}")
 
 
+def fig3_scan() -> Scan:
+    """Shape of the paper's benchmark (Fig. "timing" caption): 10,000 frames of
+    128 x 128 from a 1000 x 1000 image with periodic boundaries and a known
+    probe.  The paper's object and zone-plate probe are not available; the
+    stand-ins are the i.i.d. object of workload 1 and a Fresnel-propagated
+    aperture (radius 30 px, Fresnel number 10).  Raster step 10 px, 100 x 100
+    positions, noiseless, start image U[0,1)."""
+    st = streams_for(1602 * 10 + 6)
+    n, m, step = 1000, 128, 10
+    pos = np.array([(step * j, step * k) for j in range(n // step) for k in range(n // step)], dtype=np.int32)
+    return Scan("fig3-1000-128x10000-periodic", n, m, pos, random_object(st["object"], n, n),
+                fresnel_aperture_probe(m, 30.0, 10.0), _start_object(st["init"], n), None, 0.75, 2000, 0, 1,
+                True, st)
+
+
 def gradient_point(scan: Scan):
     """Evaluation point of the gradient workloads: psi = U[0,1) real (the start
     object), w = w_true (1 + 0.1 xi) with xi ~ N(0,1) real from the init stream

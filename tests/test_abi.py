@@ -73,7 +73,7 @@ def test_validation(L):
     assert _create(L, 64, 32, [(0, 0)], tile=24)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], reserved=1)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], eps_D=-1.0)[0] == -1
-    assert _create(L, 64, 32, [(0, 0)], frame_launch=2)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], frame_launch=3)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], fft_block=64)[0] == -1
     assert _create(L, 300, 256, [(0, 0)], fft_block=512)[0] == 0
     h = ctypes.c_void_p()
