@@ -31,7 +31,7 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = "frames/s per RAAR iteration + achieved HBM GB/s (% peak), plain vs batched/grad"
 
 
-def algorithmic_bytes(K: int, m: int, n: int) -> dict:
+def algorithmic_bytes(K: int, m: int, n: int, form: int = 1) -> dict:
     """Bytes the method itself must move per iteration, attributed to the
     kernel that moves them (intermediates an implementation adds are not
     counted).  Per frame pixel: carry read 8, amplitudes 4, carry write 8,
@@ -39,16 +39,23 @@ def algorithmic_bytes(K: int, m: int, n: int) -> dict:
     gathered object read 8, D^-1 read 4, object write 8 (20 B)."""
     fp = K * m * m
     op = n * n
-    out = {"iteration": 36 * fp + 20 * op, "merge": 8 * fp + 12 * op}
-    if m == 256:   # three passes: row (carry + gather), column (amplitudes), output row (writes)
-        out.update({"frame": 8 * fp + 8 * op, "cols": 4 * fp, "frame_out": 16 * fp})
-    else:          # one fused frame kernel
-        out.update({"frame": 28 * fp + 8 * op})
+    out = {"iteration": 36 * fp + 20 * op}
+    if m == 256 and form == 2:   # Fourier-domain carry: gather + rows, columns with the carry, strip merge
+        out.update({"frame": 8 * op, "cols": 28 * fp, "merge": 8 * fp + 12 * op})
+    elif m == 256:               # three passes: row (carry + gather), column (amplitudes), output row (writes)
+        out.update({"frame": 8 * fp + 8 * op, "cols": 4 * fp, "frame_out": 16 * fp, "merge": 8 * fp + 12 * op})
+    else:                        # one fused frame kernel
+        out.update({"frame": 28 * fp + 8 * op, "merge": 8 * fp + 12 * op})
     return out
 
 
-KERNEL_NAMES = {"frame": "mp_row_fwd<256, RAAR> / fg_kernel<m, RAAR>", "cols": "mp_col<256, RAAR>",
-                "frame_out": "mp_row_inv<256, RAAR>", "merge": "merge_kernel<T, MK_V>"}
+def kernel_names(m: int, form: int) -> dict:
+    if m == 256 and form == 2:
+        return {"frame": "mp_row_fwd<256, GATHER>", "cols": "col_carry_kernel", "merge": "strip_merge_kernel"}
+    if m == 256:
+        return {"frame": "mp_row_fwd<256, RAAR>", "cols": "mp_col<256, RAAR>", "frame_out": "mp_row_inv<256, RAAR>",
+                "merge": "merge_kernel<T, MK_V>"}
+    return {"frame": f"fg_kernel<{m}, RAAR>", "merge": "merge_kernel<T, MK_V>"}
 
 
 def gpu_workload(steps: int, warmup: int, timing: bool, fft_block: int = 0):
@@ -290,7 +297,8 @@ def main() -> int:
     plan.sync()
     ms_step = ms / args.steps
     fps = s.K / (ms_step / 1e3)
-    B = algorithmic_bytes(s.K, s.m, s.n)
+    form = plan.info()["frame_launch"]
+    B = algorithmic_bytes(s.K, s.m, s.n, form)
     out = {
         "metric": METRIC,
         "value": round(fps, 1),
@@ -307,6 +315,7 @@ def main() -> int:
         "config": {"workload": "large-frame RAAR: object 2048x2048, 2025 frames 256x256, step 40 jitter 2, "
                                "1e8 photons/frame, beta 0.75, known probe",
                    "object": s.n, "frame": s.m, "frames": s.K, "beta": s.beta,
+                   "frame_launch": form, "strip_rows": plan.info()["strip_rows"],
                    "fft_block": plan.info()["fft_block"], "merge_tile": plan.info()["tile"],
                    "merge_split": plan.info()["merge_split"]},
         "achieved_alg_GBps": round(B["iteration"] / (ms_step / 1e3) / 1e9, 1),
@@ -321,7 +330,7 @@ def main() -> int:
         ach = B[dom] / (per[dom]["ms_mean"] / 1e3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom),
-                           "kernel": KERNEL_NAMES.get(dom, dom), "alg_bytes_per_launch": B[dom],
+                           "kernel": kernel_names(s.m, form).get(dom, dom), "alg_bytes_per_launch": B[dom],
                            "launch_ms": per[dom]["ms_mean"]}
     del plan
     if not args.no_forms:

@@ -76,7 +76,9 @@ typedef struct sharp_options {
                          domain, merge fused into the last (inverse row) pass */
     int fft_block;    /* m = 256, form 1: threads per pass workgroup, 128, 256 or 512 (8, 16
                          or 32 rows / columns per workgroup); 0 = 256 */
-    int reserved[3];  /* must be zero */
+    int strip_rows;   /* m = 256, form 2: object rows per merge strip, 1 or 2 (0 = default,
+                         1); 2 is taken only while 2 nx <= 8192 */
+    int reserved[2];  /* must be zero */
 } sharp_options;
 
 /* ------------------------------------------------------------------------
@@ -204,6 +206,7 @@ int sharp_set_state(sharp_plan plan, const void* d_state);
 typedef struct sharp_plan_info {
     int nx, ny, m, K, periodic;
     int tile, tiles_x, tiles_y, merge_split, grad_groups, frame_launch, fft_block;
+    int strip_rows;           /* form 2: object rows per merge strip (0 in form 1) */
     long long csr_nnz;        /* (tile, frame) incidences */
     long long iteration;      /* iterations run since sharp_set_object */
 } sharp_plan_info;

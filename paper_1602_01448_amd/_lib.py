@@ -35,13 +35,14 @@ class SharpError(RuntimeError):
 class SharpOptions(Structure):
     _fields_ = [("periodic", c_int), ("probe_every", c_int), ("probe_start", c_int), ("eps_D", c_float),
                 ("tile", c_int), ("merge_split", c_int), ("grad_groups", c_int), ("frame_launch", c_int),
-                ("fft_block", c_int), ("reserved", c_int * 3)]
+                ("fft_block", c_int), ("strip_rows", c_int), ("reserved", c_int * 2)]
 
 
 class SharpPlanInfo(Structure):
     _fields_ = [("nx", c_int), ("ny", c_int), ("m", c_int), ("K", c_int), ("periodic", c_int),
                 ("tile", c_int), ("tiles_x", c_int), ("tiles_y", c_int), ("merge_split", c_int),
-                ("grad_groups", c_int), ("frame_launch", c_int), ("fft_block", c_int), ("csr_nnz", c_longlong),
+                ("grad_groups", c_int), ("frame_launch", c_int), ("fft_block", c_int), ("strip_rows", c_int),
+                ("csr_nnz", c_longlong),
                 ("iteration", c_longlong)]
 
 

@@ -953,57 +953,118 @@ __global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
 
 // Inverse row FFTs of the frame rows that land in object strip s (SH rows),
 // multiplied by conj(w) and summed in ascending frame order into the strip,
-// then psi_v = D^+ * sum.  A thread owns object columns t, t + 256, ... of the
-// strip, so the per-pixel order of the sum is the frame order and no two
-// threads touch one pixel.
+// then psi_v = D^+ * sum.  Thread t owns the strip pixels whose column is
+// congruent to t modulo 256, so the per-pixel order of the sum is the frame
+// order and no two threads touch one pixel.
+//
+// Lines are taken LINES at a time (LINES / SH frames).  Lane l of every wave
+// holds the record (frame, frame row, frame x) of line l of a batch; the
+// per-line values are read from that lane, so a batch costs one small load
+// of records, fetched a batch ahead.  When every frame's columns map onto
+// residues without wrap trouble (no periodic wrap, or nx a multiple of 256)
+// thread t loads, for each line, the one frame column x with px + x = t
+// (mod 256), and w at that pixel while the batch is transformed, so the sum
+// needs no further memory access; the next batch of lines is loaded while the
+// current one is transformed and summed.  Otherwise (periodic wrap with nx not a multiple of
+// 256) a thread walks its own columns and reads w per use.
+
+constexpr int kStripLines = 16;
+
+__device__ __forceinline__ int4 strip_records(const StripArgs& S, int i, int e, int lane) {
+    int4 rec = make_int4(-1, 0, 0, 0);
+    const int fk = S.SH == 2 ? (lane >> 1) : lane;
+    if (lane < kStripLines && i + fk < e) rec = S.lines[(unsigned)i * S.SH + lane];
+    return rec;
+}
 
 __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int strip, float2* lds, const float2* twl,
                                  float2* acc) {
-    constexpr int M = 256, NT = 256, NP = 8, LINES = 16, MM = M * M;
-    const int tid = opaque_tid();
+    constexpr int M = 256, NT = 256, LINES = kStripLines, MM = M * M;
+    const int tid = opaque_tid(), lane = tid & 63;
     const int SH = S.SH, FPB = LINES / SH, nx = A.nx, ny = A.ny;
     const int y0 = strip * SH;
     for (int i = tid; i < SH * nx; i += NT) acc[i] = make_float2(0.f, 0.f);
     const int b = S.ptr[strip], e = S.ptr[strip + 1];
     const float inv_m = 1.0f / M;
-    for (int i = b; i < e; i += FPB) {
+    NoPost none;
+#define LINE_F(rec, l) __builtin_amdgcn_readlane((rec).x, (l))
+#define LINE_R(rec, l) __builtin_amdgcn_readlane((rec).y, (l))
+#define LINE_PX(rec, l) __builtin_amdgcn_readlane((rec).z, (l))
+    int4 cur = strip_records(S, b, e, lane);
+    if (!A.periodic || (nx & (M - 1)) == 0) {
+        float2 v[LINES], wv[LINES];
+        auto issue = [&](const int4& rec, bool frames, float2* dst) {
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int e0 = 2 * (tid + NT * k);
-            const int line = e0 / M, x = e0 % M, fk = line / SH, sr = line % SH;
-            float2 v0 = make_float2(0.f, 0.f), v1 = v0;
-            if (i + fk < e) {
-                const int f = S.frames[i + fk];
-                int r = y0 + sr - A.pos[2 * f];
-                if (A.periodic && r < 0) r += ny;
-                if ((unsigned)r < (unsigned)M && y0 + sr < ny) ld2(A.stage + (size_t)f * MM, r * M + x, v0, v1);
+            for (int l = 0; l < LINES; ++l) {
+                const int f = LINE_F(rec, l);
+                dst[l] = make_float2(0.f, 0.f);
+                if (f >= 0) {
+                    const unsigned x = (unsigned)(tid - LINE_PX(rec, l)) & (M - 1);
+                    const unsigned o = (unsigned)LINE_R(rec, l) * M + x;
+                    dst[l] = frames ? ldc(A.stage + (size_t)f * MM, o) : ldc(A.w, o);
+                }
             }
-            lds[pidx(e0)] = v0;
-            lds[pidx(e0 + 1)] = v1;
+        };
+        issue(cur, true, v);
+        int4 next = strip_records(S, b + FPB, e, lane);
+        for (int i = b; i < e; i += FPB) {
+#pragma unroll
+            for (int l = 0; l < LINES; ++l) {
+                const unsigned x = (unsigned)(tid - LINE_PX(cur, l)) & (M - 1);
+                lds[pidx(l * M + x)] = v[l];
+            }
+            __syncthreads();
+            issue(cur, false, wv);                  // w of this batch (cache resident)
+            if (i + FPB < e) issue(next, true, v);  // next batch's lines, in flight during the FFT
+            const int4 after = strip_records(S, i + 2 * FPB, e, lane);
+            fft_1d<M, -1, NT, LINES, RowLay<M>>(lds, twl, none);
+#pragma unroll
+            for (int l = 0; l < LINES; ++l) {
+                if (LINE_F(cur, l) < 0) continue;
+                const int px = LINE_PX(cur, l);
+                const int x = (tid - px) & (M - 1);
+                int gx = px + x;
+                if (gx >= nx) gx -= nx;
+                const float2 yv = cscale(lds[pidx(l * M + x)], inv_m);
+                float2& a = acc[(SH == 2 ? (l & 1) : 0) * nx + gx];
+                a = cadd(a, cconjmul(wv[l], yv));
+            }
+            __syncthreads();
+            cur = next;
+            next = after;
         }
-        __syncthreads();
-        NoPost none;
-        fft_1d<M, -1, NT, LINES, RowLay<M>>(lds, twl, none);
-        for (int fk = 0; fk < FPB && i + fk < e; ++fk) {
-            const int f = S.frames[i + fk];
-            const int py = A.pos[2 * f], px = A.pos[2 * f + 1];
-            for (int sr = 0; sr < SH; ++sr) {
-                int r = y0 + sr - py;
-                if (A.periodic && r < 0) r += ny;
-                if ((unsigned)r >= (unsigned)M || y0 + sr >= ny) continue;
+    } else {
+        for (int i = b; i < e; i += FPB) {
+#pragma unroll
+            for (int l = 0; l < LINES; ++l) {
+                const int f = LINE_F(cur, l);
+                float2 v = make_float2(0.f, 0.f);
+                if (f >= 0) v = ldc(A.stage + (size_t)f * MM, (unsigned)LINE_R(cur, l) * M + tid);
+                lds[pidx(l * M + tid)] = v;
+            }
+            __syncthreads();
+            fft_1d<M, -1, NT, LINES, RowLay<M>>(lds, twl, none);
+            for (int l = 0; l < LINES; ++l) {
+                if (__builtin_amdgcn_readlane(cur.x, l) < 0) continue;
+                const int r = __builtin_amdgcn_readlane(cur.y, l), px = __builtin_amdgcn_readlane(cur.z, l);
+                const int sr = SH == 2 ? (l & 1) : 0;
                 for (int gx = tid; gx < nx; gx += NT) {
                     int x = gx - px;
-                    if (A.periodic && x < 0) x += nx;
+                    if (x < 0) x += nx;
                     if ((unsigned)x >= (unsigned)M) continue;
-                    const float2 yv = cscale(lds[pidx((fk * SH + sr) * M + x)], inv_m);
+                    const float2 yv = cscale(lds[pidx(l * M + x)], inv_m);
                     const float2 wv = ldc(A.w, (unsigned)(r * M + x));
                     float2& a = acc[sr * nx + gx];
                     a = cadd(a, cconjmul(wv, yv));
                 }
             }
+            __syncthreads();
+            cur = strip_records(S, i + FPB, e, lane);
         }
-        __syncthreads();
     }
+#undef LINE_F
+#undef LINE_R
+#undef LINE_PX
     for (int sr = 0; sr < SH; ++sr) {
         const int y = y0 + sr;
         if (y >= ny) break;
@@ -1154,7 +1215,7 @@ size_t strip_smem_bytes(int SH, int nx) {
     return (size_t)(pidx(16 * 256) + 256 + SH * nx) * sizeof(float2);
 }
 
-hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int* strip_frames, int SH,
+hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int4* strip_lines, int SH,
                                  int nstrips, const float* Dinv, float2* psi_out, hipStream_t s, const Timer* tp,
                                  int* blocks_used) {
     const Timer& t = tp ? *tp : kNoTimer;
@@ -1175,7 +1236,7 @@ hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const
         if (e != hipSuccess) return e;
         attr = true;
     }
-    StripArgs S{strip_ptr, strip_frames, Dinv, psi_out, SH};
+    StripArgs S{strip_ptr, strip_lines, Dinv, psi_out, SH};
     t.begin(TC_MERGE);
     hipLaunchKernelGGL(strip_merge_kernel, dim3(nstrips), dim3(256), smem, s, A, S);
     t.end(TC_MERGE);

@@ -22,7 +22,7 @@ inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
 
 struct Offsets {
     size_t tw, pos, tile_ptr, tile_frames, a, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
-    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sfr, total;
+    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sln, total;
 };
 
 }  // namespace sharp
@@ -34,7 +34,7 @@ struct sharp_plan_s {
     int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
     int frame_launch = 1;     // m = 256: 1 = three passes + tile merge; 2 = Fourier carry + strip merge
     int SH = 0, nstrips = 0;  // strip merge: object rows per strip (0 = form unavailable)
-    std::vector<int32_t> strip_ptr, strip_frames;
+    std::vector<int32_t> strip_ptr, strip_lines;  // strip_lines: 4 ints per (entry, strip row)
     int fft_block = 256;      // m = 256, three launches: threads per pass workgroup
     std::vector<int32_t> tile_ptr, tile_frames;
     sharp::Offsets off{};

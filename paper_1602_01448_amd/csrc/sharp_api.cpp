@@ -96,7 +96,8 @@ static void build_csr(sharp_plan_s& p) {
     }
 }
 
-// Frames touching each strip of SH object rows, ascending (strip merge).
+// Frames touching each strip of SH object rows, ascending (strip merge), and
+// for each (frame, strip row) the frame row that lands there.
 static void build_strips(sharp_plan_s& p) {
     p.nstrips = (p.ny + p.SH - 1) / p.SH;
     std::vector<int> count(p.nstrips, 0), hit;
@@ -116,12 +117,25 @@ static void build_strips(sharp_plan_s& p) {
     }
     p.strip_ptr.assign(p.nstrips + 1, 0);
     for (int t = 0; t < p.nstrips; ++t) p.strip_ptr[t + 1] = p.strip_ptr[t] + count[t];
-    p.strip_frames.assign(p.strip_ptr[p.nstrips], 0);
+    std::vector<int> frames(p.strip_ptr[p.nstrips], 0);
     std::vector<int> fill(p.strip_ptr.begin(), p.strip_ptr.end() - 1);
     for (int i = 0; i < p.K; ++i) {
         strips_of(i, hit);
-        for (int sidx : hit) p.strip_frames[fill[sidx]++] = i;
+        for (int sidx : hit) frames[fill[sidx]++] = i;
     }
+    p.strip_lines.assign(frames.size() * p.SH * 4, 0);
+    for (int sidx = 0; sidx < p.nstrips; ++sidx)
+        for (int j = p.strip_ptr[sidx]; j < p.strip_ptr[sidx + 1]; ++j)
+            for (int sr = 0; sr < p.SH; ++sr) {
+                const int f = frames[j], y = sidx * p.SH + sr;
+                int r = y - p.pos[2 * f];
+                if (r < 0) r += p.ny;  // periodic only (else the frame does not reach y)
+                int32_t* rec = &p.strip_lines[((size_t)j * p.SH + sr) * 4];
+                const bool hit_row = y < p.ny && r < p.m;
+                rec[0] = hit_row ? f : -1;
+                rec[1] = hit_row ? r : 0;
+                rec[2] = hit_row ? p.pos[2 * f + 1] : 0;
+            }
 }
 
 static void choose_tuning(sharp_plan_s& p) {
@@ -146,7 +160,7 @@ static void choose_tuning(sharp_plan_s& p) {
     p.fft_block = p.opt.fft_block ? p.opt.fft_block : 256;
     // m = 256: Fourier-domain carry with the merge fused into the last row pass
     // unless asked otherwise; needs a strip of the object in LDS
-    p.SH = p.m != 256 ? 0 : p.nx <= 4096 ? 2 : p.nx <= 8192 ? 1 : 0;
+    p.SH = p.m != 256 || p.nx > 8192 ? 0 : (p.opt.strip_rows == 2 && 2 * p.nx <= 8192) ? 2 : 1;
     p.frame_launch = p.opt.frame_launch ? p.opt.frame_launch : (p.m == 256 ? 2 : 1);
     if (p.frame_launch == 2 && !p.SH) p.frame_launch = 1;
     if (p.m != 256) p.frame_launch = 1;
@@ -191,7 +205,7 @@ static void layout(sharp_plan_s& p) {
     o.scal = take(16 * sizeof(float));
     o.flag = take(16 * sizeof(int));
     o.sptr = take((p.strip_ptr.size() + 1) * sizeof(int32_t));
-    o.sfr = take((p.strip_frames.size() + 1) * sizeof(int32_t));
+    o.sln = take((p.strip_lines.size() + 4) * sizeof(int32_t));
     o.total = cur;
 }
 
@@ -211,7 +225,8 @@ extern "C" int sharp_plan_create(sharp_plan* out, int nx, int ny, int m, int K, 
         if (o.periodic < 0 || o.periodic > 1 || o.probe_every < 0 || o.probe_start < 0 || !(o.eps_D >= 0.f) ||
             !(o.tile == 0 || o.tile == 16 || o.tile == 32 || o.tile == 64) || o.merge_split < 0 ||
             o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 2 ||
-            !(o.fft_block == 0 || o.fft_block == 128 || o.fft_block == 256 || o.fft_block == 512))
+            !(o.fft_block == 0 || o.fft_block == 128 || o.fft_block == 256 || o.fft_block == 512) ||
+            o.strip_rows < 0 || o.strip_rows > 2)
             return SHARP_ERR_INVALID_ARG;
     }
     if (o.probe_start == 0) o.probe_start = 1;
@@ -282,7 +297,7 @@ extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
     if (!p->strip_ptr.empty()) {
         HIPCHK(hipMemcpyAsync(p->ws + p->off.sptr, p->strip_ptr.data(), p->strip_ptr.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(p->ws + p->off.sfr, p->strip_frames.data(), p->strip_frames.size() * sizeof(int32_t),
+        HIPCHK(hipMemcpyAsync(p->ws + p->off.sln, p->strip_lines.data(), p->strip_lines.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, s));
     }
     HIPCHK(launch_fill(p->ws + p->off.hist, kHistCap * sizeof(float), s));
@@ -442,7 +457,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     const Timer* t = p.tm();
     if (p.carry_form()) {
         // frame phase and merge in one sequence; psi_v is final afterwards
-        HIPCHK(launch_carry_raar_256(A, p.at<int>(p.off.sptr), p.at<int>(p.off.sfr), p.SH, p.nstrips,
+        HIPCHK(launch_carry_raar_256(A, p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.SH, p.nstrips,
                                      p.at<float>(p.off.Dinv), p.at<float2>(p.off.psi_v), s, t, &blocks));
     } else if (p.m == 256) {
         HIPCHK(launch_raar_mp256(A, p.fft_block, s, t, &blocks));
@@ -752,6 +767,7 @@ extern "C" int sharp_get_plan_info(sharp_plan p, sharp_plan_info* info) {
     info->grad_groups = p->grad_groups;
     info->frame_launch = p->frame_launch;
     info->fft_block = p->fft_block;
+    info->strip_rows = p->carry_form() ? p->SH : 0;
     info->csr_nnz = (long long)p->tile_frames.size();
     info->iteration = p->iter;
     return SHARP_OK;

@@ -118,8 +118,10 @@ hipError_t launch_raar_mp256(const FrameArgs& A, int threads, hipStream_t s, con
 // m = 256 RAAR with the carry in the Fourier domain and the merge fused into
 // the last row pass (kernels_frame.hip).  Strip merge arguments:
 struct StripArgs {
-    const int* __restrict__ ptr;     // [nstrips + 1]
-    const int* __restrict__ frames;  // frames touching each strip, ascending
+    const int* __restrict__ ptr;     // [nstrips + 1] entries (frames) per strip
+    const int4* __restrict__ lines;  // [entries * SH]: (frame, frame row, frame x, 0) of the frame
+                                     // row landing on each strip row, frame -1 when none; frames
+                                     // ascending within a strip
     const float* __restrict__ Dinv;
     float2* __restrict__ out;        // psi_v
     int SH;                          // object rows per strip
@@ -129,7 +131,7 @@ hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu);
 hipError_t launch_batch_carry(int phase, const FrameArgs* D, const StripArgs* SD, const int2* items, int n, int grid,
                               size_t smem, hipStream_t s);
 size_t strip_smem_bytes(int SH, int nx);
-hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int* strip_frames, int SH,
+hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int4* strip_lines, int SH,
                                  int nstrips, const float* Dinv, float2* psi_out, hipStream_t s, const Timer* t,
                                  int* blocks_used);
 hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s);

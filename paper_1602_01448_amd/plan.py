@@ -32,7 +32,8 @@ class Plan:
 
     def __init__(self, nx: int, ny: int, m: int, positions, periodic: bool = False, probe_every: int = 0,
                  probe_start: int = 1, eps_D: float = 0.0, tile: int = 0, merge_split: int = 0,
-                 grad_groups: int = 0, frame_launch: int = 0, fft_block: int = 0, device="cuda"):
+                 grad_groups: int = 0, frame_launch: int = 0, fft_block: int = 0, strip_rows: int = 0,
+                 device="cuda"):
         pos = np.ascontiguousarray(np.asarray(positions), dtype=np.int32)
         if pos.ndim != 2 or pos.shape[1] != 2:
             raise ValueError("positions must be (K, 2) (y, x)")
@@ -41,7 +42,7 @@ class Plan:
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         opts = SharpOptions(int(periodic), int(probe_every), int(probe_start), float(eps_D), int(tile),
-                            int(merge_split), int(grad_groups), int(frame_launch), int(fft_block))
+                            int(merge_split), int(grad_groups), int(frame_launch), int(fft_block), int(strip_rows))
         h = c_void_p()
         check(lib.sharp_plan_create(byref(h), self.nx, self.ny, self.m, self.K,
                                     pos.ctypes.data_as(POINTER(c_int32)), byref(opts)), "sharp_plan_create")

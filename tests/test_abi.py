@@ -41,7 +41,7 @@ def _create(L, n, m, pos, **kw):
     pos = np.ascontiguousarray(pos, dtype=np.int32)
     opts = SharpOptions(kw.get("periodic", 0), kw.get("probe_every", 0), kw.get("probe_start", 1),
                         kw.get("eps_D", 0.0), kw.get("tile", 0), kw.get("merge_split", 0), kw.get("grad_groups", 0),
-                        kw.get("frame_launch", 0), kw.get("fft_block", 0))
+                        kw.get("frame_launch", 0), kw.get("fft_block", 0), kw.get("strip_rows", 0))
     if "reserved" in kw:
         opts.reserved[0] = kw["reserved"]
     st = L.sharp_plan_create(ctypes.byref(h), n, n, m, len(pos), pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -75,10 +75,26 @@ def test_validation(L):
     assert _create(L, 64, 32, [(0, 0)], eps_D=-1.0)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], frame_launch=3)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], fft_block=64)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], strip_rows=3)[0] == -1
     assert _create(L, 300, 256, [(0, 0)], fft_block=512)[0] == 0
     h = ctypes.c_void_p()
     assert L.sharp_plan_create(ctypes.byref(h), 64, 64, 32, 0, None, None) == -1
     assert L.sharp_plan_create(None, 64, 64, 32, 1, None, None) == -1
+
+
+@pytest.mark.parametrize("n,kw,form,rows", [(300, {}, 2, 1), (300, {"strip_rows": 2}, 2, 2),
+                                           (5000, {"strip_rows": 2}, 2, 1), (9000, {}, 1, 0),
+                                           (300, {"frame_launch": 1}, 1, 0)])
+def test_large_frame_form_selection(L, n, kw, form, rows):
+    """m = 256: Fourier-carry form with 1-row strips by default, 2-row strips
+    on request while a 2-row strip fits in LDS, frame-space form beyond 8192."""
+    from paper_1602_01448_amd._lib import SharpPlanInfo
+    st, h = _create(L, n, 256, [(0, 0), (n - 256, n - 256)], **kw)
+    assert st == 0
+    info = SharpPlanInfo()
+    assert L.sharp_get_plan_info(h, ctypes.byref(info)) == 0
+    assert (info.frame_launch, info.strip_rows) == (form, rows)
+    L.sharp_plan_destroy(h)
 
 
 def test_calls_before_workspace_are_not_ready(L):

@@ -226,9 +226,9 @@ def test_large_frame_pass_block_sizes(block):
     assert np.max(np.abs(got["eps"] - ref["eps_a"]) / ref["eps_a"]) < 1e-4
 
 
-@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("form,rows", [(1, 0), (2, 1), (2, 2)])
 @pytest.mark.parametrize("periodic", [False, True])
-def test_large_frame_forms_match_oracle(form, periodic):
+def test_large_frame_forms_match_oracle(form, rows, periodic):
     """Both m = 256 forms (frame-space carry + tile merge; Fourier-domain carry
     + strip merge) against the oracle, with and without periodic wrap."""
     rng = np.random.default_rng(5 + form)
@@ -239,8 +239,8 @@ def test_large_frame_forms_match_oracle(form, periodic):
         pos = gen.raster_positions(7, 74.67, n, m, jitter=2, rng=rng)
     s = gen.Scan("forms", n, m, pos, gen.random_object(rng, n, n), gen.fresnel_aperture_probe(m, 60.0, 10.0),
                  rng.uniform(0, 1, (n, n)).astype(complex), None, 0.75, 4, 0, 1, periodic, None)
-    p, got, ref, D = _run_both(s, 4, frame_launch=form)
-    assert p.info()["frame_launch"] == form
+    p, got, ref, D = _run_both(s, 4, frame_launch=form, strip_rows=rows)
+    assert p.info()["frame_launch"] == form and p.info()["strip_rows"] == rows
     assert dweighted(got["psi"], ref["psi"], D) < 1e-4
     assert np.max(np.abs(got["eps"] - ref["eps_a"]) / ref["eps_a"]) < 1e-4
 
