@@ -103,6 +103,16 @@ __device__ __forceinline__ float2 ldc(const float2* __restrict__ p, unsigned i) 
     return *reinterpret_cast<const float2*>(byte_at(p, i, 8u));
 }
 
+// g * w * psi for the gather of the m = 256 carry form (row pass and strip
+// pass), evaluated without contraction.
+__device__ __forceinline__ float2 gather_z(float2 w, float2 p, float g) {
+#pragma clang fp contract(off)
+    return make_float2((w.x * p.x - w.y * p.y) * g, (w.x * p.y + w.y * p.x) * g);
+}
+__device__ __forceinline__ void stc(float2* __restrict__ p, unsigned i, float2 v) {
+    *reinterpret_cast<float2*>(const_cast<char*>(byte_at(p, i, 8u))) = v;
+}
+
 // Gather of two horizontally adjacent object pixels for frame pixel (y, x), (y, x+1).
 __device__ __forceinline__ void gather2(const FrameArgs& A, int frame, int y, int x, float2& p0, float2& p1) {
     const int py = A.pos[2 * frame], px = A.pos[2 * frame + 1];
@@ -136,8 +146,8 @@ __device__ __forceinline__ void prologue2(const FrameArgs& A, int frame, int y, 
         float2 p0, p1, w0, w1;
         gather2(A, frame, y, x, p0, p1);
         ld2(A.w_g, pix, w0, w1);
-        z0 = cscale(cmul(w0, p0), A.g);
-        z1 = cscale(cmul(w1, p1), A.g);
+        z0 = gather_z(w0, p0, A.g);
+        z1 = gather_z(w1, p1, A.g);
     } else {  // GRAD, SIM, Q
         float2 w0, w1;
         gather2(A, frame, y, x, t0, t1);
@@ -895,6 +905,11 @@ __device__ float col_carry_item(const FrameArgs& A, int it, float2* lds, const f
     static_assert(CB == 16, "column block must match the cb256 layout");
     const int frame = it / NCB, cb = it % NCB;
     const size_t fb = (size_t)frame * MM;
+    // LDS element e0 = y * 16 + c is also the offset of (y, 16 cb + c) inside
+    // this block of the cb256 layout: the carry and amplitudes of the block are
+    // fetched with the stage columns, ahead of the column FFTs
+    const size_t blk = fb + (size_t)cb * M * CB;
+    float2 uc[2 * NP], ac[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int e0 = 2 * (tid + NT * k);
@@ -904,20 +919,23 @@ __device__ float col_carry_item(const FrameArgs& A, int it, float2* lds, const f
         lds[pidx(e0)] = a0;
         lds[pidx(e0 + 1)] = a1;
     }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e0 = 2 * (tid + NT * k);
+        ld2(A.u + blk, e0, uc[2 * k], uc[2 * k + 1]);
+        ac[k] = ldf2(A.a + blk, e0);
+    }
     __syncthreads();
     NoPost none;
     fft_1d<M, 1, NT, CB, ColLayCB<CB>>(lds, twl, none);
-    // pointwise in the Fourier domain; LDS element e0 = y * 16 + c is also the
-    // offset of (y, 16 cb + c) inside this block of the cb256 layout
-    const size_t blk = fb + (size_t)cb * M * CB;
+    // pointwise in the Fourier domain
     const float inv_m = 1.0f / M, b = A.beta, c1 = 1.f - 2.f * A.beta;
     ModOp<FM_RAAR, M> op{nullptr, nullptr, 0.f};
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int e0 = 2 * (tid + NT * k);
-        float2 u0, u1;
-        ld2(A.u + blk, e0, u0, u1);
-        const float2 av = ldf2(A.a + blk, e0);
+        const float2 u0 = uc[2 * k], u1 = uc[2 * k + 1];
+        const float2 av = ac[k];
         const float2 z0 = cadd(u0, cscale(lds[pidx(e0)], inv_m));
         const float2 z1 = cadd(u1, cscale(lds[pidx(e0 + 1)], inv_m));
         const float2 y0 = op.modulus(z0, av.x, true), y1 = op.modulus(z1, av.y, true);
@@ -957,16 +975,22 @@ __global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
 // congruent to t modulo 256, so the per-pixel order of the sum is the frame
 // order and no two threads touch one pixel.
 //
-// Lines are taken LINES at a time (LINES / SH frames).  Lane l of every wave
-// holds the record (frame, frame row, frame x) of line l of a batch; the
-// per-line values are read from that lane, so a batch costs one small load
-// of records, fetched a batch ahead.  When every frame's columns map onto
-// residues without wrap trouble (no periodic wrap, or nx a multiple of 256)
-// thread t loads, for each line, the one frame column x with px + x = t
-// (mod 256), and w at that pixel while the batch is transformed, so the sum
-// needs no further memory access; the next batch of lines is loaded while the
-// current one is transformed and summed.  Otherwise (periodic wrap with nx not a multiple of
-// 256) a thread walks its own columns and reads w per use.
+// Lines are taken LINES = 16 at a time (16 / SH frames).  The 256-point
+// transforms keep one line in 16 threads (thread t: line t / 16, j = t mod 16)
+// and run the two radix-16 Stockham stages in registers: the first stage
+// takes its 16 inputs (elements j + 16 r) straight from global memory, one
+// LDS exchange feeds the second stage, whose twiddles W^(j r) are fixed per
+// thread and held in registers for the whole strip.  Butterflies, twiddles
+// and their order are those of the LDS transforms of the row passes; results
+// agree with them to rounding (the compiler may fuse multiplies and adds
+// differently in the two code shapes).
+//
+// Lane l of every wave also holds the record (frame, frame row, frame x) of
+// line l of a batch for the column-owned sum.  When every frame's columns map
+// onto residues without wrap trouble (no periodic wrap, or nx a multiple of
+// 256) thread t reads, for each line, the one frame column x with px + x = t
+// (mod 256); otherwise (periodic wrap with nx not a multiple of 256) a thread
+// walks its own columns and reads w per use.
 
 constexpr int kStripLines = 16;
 
@@ -977,51 +1001,146 @@ __device__ __forceinline__ int4 strip_records(const StripArgs& S, int i, int e, 
     return rec;
 }
 
+// The record of the line this thread transforms (line = tid / 16).
+__device__ __forceinline__ int4 strip_my_record(const StripArgs& S, int i, int e, int line) {
+    return strip_records(S, i, e, line);
+}
+
+// The 16 threads of a line lie in one wavefront, whose LDS accesses are
+// performed in program order: exchanges inside a line only need the compiler
+// to keep that order.
+__device__ __forceinline__ void line_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// First radix-16 stage of a 256-point line held as v[r] = element j + 16 r;
+// outputs go to LDS elements 16 j + q of the line.
+template <int DIR>
+__device__ __forceinline__ void line_stage1(float2 (&v)[16], float2* lds, int line, int j) {
+    dft<16, DIR>(v);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lds[pidx(line * 256 + 16 * j + q)] = v[q];
+}
+
+// Second stage for butterfly k = j: inputs k + 16 r from LDS, twiddles
+// W^(k r) (conjugated for the inverse), outputs v[q] = element k + 16 q.
+template <int DIR>
+__device__ __forceinline__ void line_stage2(float2 (&v)[16], const float2* lds, int line, int k,
+                                            const float2 (&tw)[15]) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = lds[pidx(line * 256 + k + 16 * r)];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) {
+        float2 t = tw[r - 1];
+        if constexpr (DIR < 0) t.y = -t.y;
+        v[r] = cmul(v[r], t);
+    }
+    dft<16, DIR>(v);
+}
+
+// The next iteration's frames are z = beta w T psi_v + u (carry form, Fourier
+// side), and the row pass of that iteration only gathers beta w T psi_v and
+// row-transforms it.  Frame row r of frame f reads object row py + r only, so
+// the strip that has just finished psi_v on its rows forms those gathered,
+// row-transformed lines itself (the row pass's transform, equal to rounding)
+// and writes them where the row pass would: the next iteration starts at the
+// column pass.  Lines are independent here, so a wavefront runs through its
+// own lines without workgroup barriers.
+__device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b, int e, float2* lds,
+                                  const float2 (&tw)[15], const float2* psi_rows) {
+    constexpr int M = 256, LINES = kStripLines, MM = M * M;
+    const int tid = opaque_tid(), line = tid >> 4, j = tid & 15;
+    const int SH = S.SH, FPB = LINES / SH, nx = A.nx;
+    const int sr = SH == 2 ? (line & 1) : 0;
+    const float g = A.beta;
+    float2 ww[16];
+    auto loadw = [&](const int4& rec) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ww[r] = rec.x >= 0 ? ldc(A.w, (unsigned)rec.y * M + j + 16 * r) : make_float2(0.f, 0.f);
+    };
+    int4 cur = strip_my_record(S, b, e, line);
+    loadw(cur);
+    for (int i = b; i < e; i += FPB) {
+        float2 v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            v[r] = make_float2(0.f, 0.f);
+            if (cur.x >= 0) {
+                int gx = cur.z + j + 16 * r;
+                if (gx >= nx) gx -= nx;
+                v[r] = gather_z(ww[r], psi_rows[sr * nx + gx], g);
+            }
+        }
+        line_stage1<1>(v, lds, line, j);
+        const int4 nxt = strip_my_record(S, i + FPB, e, line);
+        if (i + FPB < e) loadw(nxt);
+        line_sync();
+        line_stage2<1>(v, lds, line, j, tw);
+        if (cur.x >= 0) {
+            float2* dst = A.stage + (size_t)cur.x * MM + (size_t)cur.y * M;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) dst[j + 16 * q] = v[q];
+        }
+        line_sync();   // the line's LDS slots are rewritten by the next batch
+        cur = nxt;
+    }
+    __syncthreads();
+}
+
 __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int strip, float2* lds, const float2* twl,
                                  float2* acc) {
     constexpr int M = 256, NT = 256, LINES = kStripLines, MM = M * M;
-    const int tid = opaque_tid(), lane = tid & 63;
+    const int tid = opaque_tid(), lane = tid & 63, line = tid >> 4, j = tid & 15;
     const int SH = S.SH, FPB = LINES / SH, nx = A.nx, ny = A.ny;
     const int y0 = strip * SH;
     for (int i = tid; i < SH * nx; i += NT) acc[i] = make_float2(0.f, 0.f);
     const int b = S.ptr[strip], e = S.ptr[strip + 1];
     const float inv_m = 1.0f / M;
-    NoPost none;
-#define LINE_F(rec, l) __builtin_amdgcn_readlane((rec).x, (l))
-#define LINE_R(rec, l) __builtin_amdgcn_readlane((rec).y, (l))
-#define LINE_PX(rec, l) __builtin_amdgcn_readlane((rec).z, (l))
+    float2 tw[15];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) tw[r - 1] = twl[j * r];
+    const bool owned = !A.periodic || (nx & (M - 1)) == 0;
+    float2 v[16];
+    auto load_line = [&](const int4& rec) {
+        const float2* src = A.stage + (size_t)(rec.x < 0 ? 0 : rec.x) * MM + (size_t)rec.y * M + j;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = rec.x >= 0 ? src[16 * r] : make_float2(0.f, 0.f);
+    };
+    int4 mine = strip_my_record(S, b, e, line);
     int4 cur = strip_records(S, b, e, lane);
-    if (!A.periodic || (nx & (M - 1)) == 0) {
-        float2 v[LINES], wv[LINES];
-        auto issue = [&](const int4& rec, bool frames, float2* dst) {
+    load_line(mine);
+    for (int i = b; i < e; i += FPB) {
+        line_stage1<-1>(v, lds, line, j);
+        const int4 mine_next = strip_my_record(S, i + FPB, e, line);
+        const int4 next = strip_records(S, i + FPB, e, lane);
+        if (i + FPB < e) load_line(mine_next);   // next batch in flight during this one
+        float2 wv[LINES];
+        if (owned) {
 #pragma unroll
             for (int l = 0; l < LINES; ++l) {
-                const int f = LINE_F(rec, l);
-                dst[l] = make_float2(0.f, 0.f);
-                if (f >= 0) {
-                    const unsigned x = (unsigned)(tid - LINE_PX(rec, l)) & (M - 1);
-                    const unsigned o = (unsigned)LINE_R(rec, l) * M + x;
-                    dst[l] = frames ? ldc(A.stage + (size_t)f * MM, o) : ldc(A.w, o);
+                wv[l] = make_float2(0.f, 0.f);
+                if (__builtin_amdgcn_readlane(cur.x, l) >= 0) {
+                    const unsigned x = (unsigned)(tid - __builtin_amdgcn_readlane(cur.z, l)) & (M - 1);
+                    wv[l] = ldc(A.w, (unsigned)__builtin_amdgcn_readlane(cur.y, l) * M + x);
                 }
             }
-        };
-        issue(cur, true, v);
-        int4 next = strip_records(S, b + FPB, e, lane);
-        for (int i = b; i < e; i += FPB) {
+        }
+        line_sync();
+        {
+            // a thread reads and writes the same 16 elements of its line here
+            float2 t[16];
+            line_stage2<-1>(t, lds, line, j, tw);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) lds[pidx(line * M + j + 16 * q)] = t[q];
+        }
+        __syncthreads();
+        if (owned) {
 #pragma unroll
             for (int l = 0; l < LINES; ++l) {
-                const unsigned x = (unsigned)(tid - LINE_PX(cur, l)) & (M - 1);
-                lds[pidx(l * M + x)] = v[l];
-            }
-            __syncthreads();
-            issue(cur, false, wv);                  // w of this batch (cache resident)
-            if (i + FPB < e) issue(next, true, v);  // next batch's lines, in flight during the FFT
-            const int4 after = strip_records(S, i + 2 * FPB, e, lane);
-            fft_1d<M, -1, NT, LINES, RowLay<M>>(lds, twl, none);
-#pragma unroll
-            for (int l = 0; l < LINES; ++l) {
-                if (LINE_F(cur, l) < 0) continue;
-                const int px = LINE_PX(cur, l);
+                if (__builtin_amdgcn_readlane(cur.x, l) < 0) continue;
+                const int px = __builtin_amdgcn_readlane(cur.z, l);
                 const int x = (tid - px) & (M - 1);
                 int gx = px + x;
                 if (gx >= nx) gx -= nx;
@@ -1029,21 +1148,7 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
                 float2& a = acc[(SH == 2 ? (l & 1) : 0) * nx + gx];
                 a = cadd(a, cconjmul(wv[l], yv));
             }
-            __syncthreads();
-            cur = next;
-            next = after;
-        }
-    } else {
-        for (int i = b; i < e; i += FPB) {
-#pragma unroll
-            for (int l = 0; l < LINES; ++l) {
-                const int f = LINE_F(cur, l);
-                float2 v = make_float2(0.f, 0.f);
-                if (f >= 0) v = ldc(A.stage + (size_t)f * MM, (unsigned)LINE_R(cur, l) * M + tid);
-                lds[pidx(l * M + tid)] = v;
-            }
-            __syncthreads();
-            fft_1d<M, -1, NT, LINES, RowLay<M>>(lds, twl, none);
+        } else {
             for (int l = 0; l < LINES; ++l) {
                 if (__builtin_amdgcn_readlane(cur.x, l) < 0) continue;
                 const int r = __builtin_amdgcn_readlane(cur.y, l), px = __builtin_amdgcn_readlane(cur.z, l);
@@ -1053,30 +1158,31 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
                     if (x < 0) x += nx;
                     if ((unsigned)x >= (unsigned)M) continue;
                     const float2 yv = cscale(lds[pidx(l * M + x)], inv_m);
-                    const float2 wv = ldc(A.w, (unsigned)(r * M + x));
+                    const float2 wq = ldc(A.w, (unsigned)(r * M + x));
                     float2& a = acc[sr * nx + gx];
-                    a = cadd(a, cconjmul(wv, yv));
+                    a = cadd(a, cconjmul(wq, yv));
                 }
             }
-            __syncthreads();
-            cur = strip_records(S, i + FPB, e, lane);
         }
+        __syncthreads();
+        mine = mine_next;
+        cur = next;
     }
-#undef LINE_F
-#undef LINE_R
-#undef LINE_PX
     for (int sr = 0; sr < SH; ++sr) {
         const int y = y0 + sr;
         if (y >= ny) break;
         for (int gx = tid; gx < nx; gx += NT) {
             const unsigned o = (unsigned)y * (unsigned)nx + gx;
-            S.out[o] = cscale(acc[sr * nx + gx], S.Dinv[o]);
+            const float2 pv = cscale(acc[sr * nx + gx], S.Dinv[o]);
+            S.out[o] = pv;
+            acc[sr * nx + gx] = pv;
         }
     }
     __syncthreads();
+    if (S.next_gather) strip_gather_next(A, S, b, e, lds, tw, acc);
 }
 
-__global__ void __launch_bounds__(256) strip_merge_kernel(FrameArgs A, StripArgs S) {
+__global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripArgs S) {
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* twl = smem + pidx(16 * 256);
@@ -1105,7 +1211,7 @@ __global__ void __launch_bounds__(256) batch_carry_kernel(const FrameArgs* __res
         const int2 w = items[it];
         const FrameArgs A = D[w.x];
         if constexpr (PHASE == 0) {
-            mp_row_fwd_item<256, FM_GATHER, 256>(A, w.y, lds, twl);
+            if (A.gather) mp_row_fwd_item<256, FM_GATHER, 256>(A, w.y, lds, twl);
         } else if constexpr (PHASE == 1) {
             const float s = block_sum(col_carry_item(A, w.y, lds, twl), red);
             if (threadIdx.x == 0) A.resid[w.y] = s;
@@ -1216,14 +1322,16 @@ size_t strip_smem_bytes(int SH, int nx) {
 }
 
 hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int4* strip_lines, int SH,
-                                 int nstrips, const float* Dinv, float2* psi_out, hipStream_t s, const Timer* tp,
-                                 int* blocks_used) {
+                                 int nstrips, const float* Dinv, float2* psi_out, bool gather, bool next_gather,
+                                 hipStream_t s, const Timer* tp, int* blocks_used) {
     const Timer& t = tp ? *tp : kNoTimer;
     using C = MP<256, 256>;
     const int rows = A.K * C::NRB, cols = A.K * C::NCB;
-    t.begin(TC_FRAME);
-    hipLaunchKernelGGL((mp_row_fwd<256, FM_GATHER, 256>), dim3(rows), dim3(256), C::SMEM, s, A);
-    t.end(TC_FRAME);
+    if (gather) {
+        t.begin(TC_FRAME);
+        hipLaunchKernelGGL((mp_row_fwd<256, FM_GATHER, 256>), dim3(rows), dim3(256), C::SMEM, s, A);
+        t.end(TC_FRAME);
+    }
     t.begin(TC_COLS);
     hipLaunchKernelGGL(col_carry_kernel, dim3(cols), dim3(256), C::SMEM, s, A);
     t.end(TC_COLS);
@@ -1236,7 +1344,7 @@ hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const
         if (e != hipSuccess) return e;
         attr = true;
     }
-    StripArgs S{strip_ptr, strip_lines, Dinv, psi_out, SH};
+    StripArgs S{strip_ptr, strip_lines, Dinv, psi_out, SH, next_gather ? 1 : 0};
     t.begin(TC_MERGE);
     hipLaunchKernelGGL(strip_merge_kernel, dim3(nstrips), dim3(256), smem, s, A, S);
     t.end(TC_MERGE);

@@ -425,6 +425,7 @@ __global__ void __launch_bounds__(256) batch_begin_kernel(FrameArgs* __restrict_
     if (s >= b.n) return;
     D[s].g = b.g[s];
     D[s].beta = beta;
+    D[s].gather = b.gather[s];
     E[s].hist_idx = b.hist[s];
 }
 

@@ -46,6 +46,7 @@ struct sharp_plan_s {
     float g = 1.f;
     long long iter = 0, hist_count = 0;
     bool gat_stale = false, last_probe_updated = false;
+    bool stage_gather = false;  // carry form: stage holds the next iteration's gathered, row-transformed frames
     // kernel timing (diagnostics): pending (start, stop) event pairs per category
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;

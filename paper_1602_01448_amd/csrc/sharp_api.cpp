@@ -275,6 +275,7 @@ static int density(sharp_plan_s& p);
 
 extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
     if (!p || !d || ((uintptr_t)d % kAlign) != 0) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (bytes < p->off.total) return SHARP_ERR_WORKSPACE_TOO_SMALL;
     p->ws = (char*)d;
     p->ws_bytes = bytes;
@@ -390,6 +391,7 @@ extern "C" int sharp_set_data(sharp_plan p, const float* d_I) {
 
 extern "C" int sharp_set_probe(sharp_plan p, const void* d_w) {
     if (!p || !d_w) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws) return SHARP_ERR_NOT_READY;
     const size_t bytes = (size_t)p->m * p->m * sizeof(float2);
     HIPCHK(launch_copy(p->ws + p->off.w_cur, d_w, bytes, p->stream));
@@ -403,6 +405,7 @@ extern "C" int sharp_set_probe(sharp_plan p, const void* d_w) {
 
 extern "C" int sharp_init_probe(sharp_plan p) {
     if (!p) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws || !p->has_data) return SHARP_ERR_NOT_READY;
     hipStream_t s = p->stream;
     HIPCHK(launch_mean_amp(p->at<float>(p->off.a), p->K, p->m, p->at<float2>(p->off.tmp_w), s));
@@ -422,6 +425,7 @@ extern "C" int sharp_init_probe(sharp_plan p) {
 
 extern "C" int sharp_set_object(sharp_plan p, const void* d_psi) {
     if (!p || !d_psi) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws || !p->has_probe) return SHARP_ERR_NOT_READY;
     hipStream_t s = p->stream;
     HIPCHK(launch_copy(p->ws + p->off.psi_v, d_psi, p->obj_elems() * sizeof(float2), s));
@@ -456,9 +460,13 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     int blocks = 0;
     const Timer* t = p.tm();
     if (p.carry_form()) {
-        // frame phase and merge in one sequence; psi_v is final afterwards
+        // frame phase and merge in one sequence; psi_v is final afterwards.  The
+        // strip pass also prepares the next iteration's gather unless a probe
+        // update (which reuses the stage buffer) follows.
         HIPCHK(launch_carry_raar_256(A, p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.SH, p.nstrips,
-                                     p.at<float>(p.off.Dinv), p.at<float2>(p.off.psi_v), s, t, &blocks));
+                                     p.at<float>(p.off.Dinv), p.at<float2>(p.off.psi_v), !p.stage_gather,
+                                     !probe_due, s, t, &blocks));
+        p.stage_gather = !probe_due;
     } else if (p.m == 256) {
         HIPCHK(launch_raar_mp256(A, p.fft_block, s, t, &blocks));
     } else {
@@ -524,6 +532,7 @@ extern "C" int sharp_raar_iterate(sharp_plan p, int n, float beta) {
 // ---------------------------------------------------------------------------
 extern "C" int sharp_get_object(sharp_plan p, void* d_out) {
     if (!p || !d_out) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws || !p->has_probe || !p->has_object) return SHARP_ERR_NOT_READY;
     if (p->last_probe_updated) {
         HIPCHK(launch_copy(d_out, p->ws + p->off.psi_l, p->obj_elems() * sizeof(float2), p->stream));
@@ -581,6 +590,7 @@ extern "C" int sharp_get_metrics(sharp_plan p, float* h_eps, int max_n, int* n_w
 extern "C" int sharp_grad(sharp_plan p, const void* d_psi, const void* d_w, float* d_loss, void* d_gpsi,
                           void* d_gw) {
     if (!p || !d_psi || !d_w || !d_loss) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws || !p->has_data) return SHARP_ERR_NOT_READY;
     hipStream_t s = p->stream;
     FrameArgs A = frame_args(*p);
@@ -606,6 +616,7 @@ extern "C" int sharp_grad(sharp_plan p, const void* d_psi, const void* d_w, floa
 
 extern "C" int sharp_simulate(sharp_plan p, const void* d_psi, const void* d_w, float* d_I) {
     if (!p || !d_psi || !d_w || !d_I) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws) return SHARP_ERR_NOT_READY;
     FrameArgs A = frame_args(*p);
     A.psi = (const float2*)d_psi;
@@ -617,6 +628,7 @@ extern "C" int sharp_simulate(sharp_plan p, const void* d_psi, const void* d_w, 
 
 extern "C" int sharp_apply(sharp_plan p, int op, const void* d_in, void* d_out) {
     if (!p || !d_in || !d_out || d_in == d_out) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws) return SHARP_ERR_NOT_READY;
     if (op != SHARP_OP_F && op != SHARP_OP_FINV && !p->has_probe) return SHARP_ERR_NOT_READY;
     if (op == SHARP_OP_PA && !p->has_data) return SHARP_ERR_NOT_READY;
@@ -694,6 +706,7 @@ extern "C" size_t sharp_state_bytes(sharp_plan p) { return p ? state_layout(*p).
 
 extern "C" int sharp_get_state(sharp_plan p, void* d_state) {
     if (!p || !d_state) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws || !p->has_probe || !p->has_object) return SHARP_ERR_NOT_READY;
     const StateLayout L = state_layout(*p);
     char* d = (char*)d_state;
@@ -715,6 +728,7 @@ extern "C" int sharp_get_state(sharp_plan p, void* d_state) {
 
 extern "C" int sharp_set_state(sharp_plan p, const void* d_state) {
     if (!p || !d_state) return SHARP_ERR_INVALID_ARG;
+    p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
     if (!p->has_ws || !p->has_data) return SHARP_ERR_NOT_READY;
     const StateLayout L = state_layout(*p);
     const char* d = (const char*)d_state;

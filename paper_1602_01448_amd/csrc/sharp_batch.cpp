@@ -169,7 +169,7 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         fa[s] = frame_args(p);
         ma[s] = merge_args(p);
         sa[s] = StripArgs{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
-                          p.at<float2>(p.off.psi_v), p.SH};
+                          p.at<float2>(p.off.psi_v), p.SH, 1};
         ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),
                         p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
     }
@@ -228,7 +228,7 @@ static int enqueue_iterations(sharp_batch_s& b, int n, float beta, hipStream_t s
             for (int ph = 0; ph < (kM[c] == 256 ? 3 : 1); ++ph)
                 HIPCHK(launch_batch_frame(kM[c], ph, D, items, cnt, std::min(cnt, b.grid_frame[c][ph]), s));
         }
-        for (int ph = 0; ph < 2; ++ph) {
+        for (int ph = l == 0 ? 0 : 1; ph < 2; ++ph) {  // later gathers come from the strip phase
             const int cnt = (int)b.carry_items[ph].size();
             if (cnt)
                 HIPCHK(launch_batch_carry(ph, D, b.at<StripArgs>(b.off.sargs), b.at<int2>(b.off.citems[ph]), cnt,
@@ -260,6 +260,7 @@ extern "C" int sharp_batch_raar_iterate(sharp_batch b, int n, float beta) {
     for (int s = 0; s < bb.n; ++s) {
         bb.g[s] = b->plans[s]->g;
         bb.hist[s] = (int)(b->plans[s]->hist_count % kHistCap);
+        bb.gather[s] = b->plans[s]->stage_gather ? 0 : 1;
     }
     // order the batch stream after the caller's stream
     HIPCHK(hipEventRecord(b->ev_in, b->user));
@@ -291,6 +292,7 @@ extern "C" int sharp_batch_raar_iterate(sharp_batch b, int n, float beta) {
         p->hist_count += n;
         p->g = beta;
         p->last_probe_updated = false;
+        p->stage_gather = p->carry_form();
     }
     return SHARP_OK;
 }

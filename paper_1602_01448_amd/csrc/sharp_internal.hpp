@@ -58,6 +58,7 @@ struct FrameArgs {
     float* __restrict__ resid;          // per-block residual partials
     float2* __restrict__ gw_part;       // per-block probe-gradient partials
     float g, beta;
+    int gather;                         // batched m = 256 carry form: run the gather pass
 };
 
 struct MergeArgs {
@@ -125,6 +126,8 @@ struct StripArgs {
     const float* __restrict__ Dinv;
     float2* __restrict__ out;        // psi_v
     int SH;                          // object rows per strip
+    int next_gather;                 // also form the next iteration's gathered, row-transformed
+                                     // frame rows (w * T psi_v scaled by beta) in the stage buffer
 };
 size_t carry_phase_smem();
 hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu);
@@ -132,8 +135,8 @@ hipError_t launch_batch_carry(int phase, const FrameArgs* D, const StripArgs* SD
                               size_t smem, hipStream_t s);
 size_t strip_smem_bytes(int SH, int nx);
 hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int4* strip_lines, int SH,
-                                 int nstrips, const float* Dinv, float2* psi_out, hipStream_t s, const Timer* t,
-                                 int* blocks_used);
+                                 int nstrips, const float* Dinv, float2* psi_out, bool gather, bool next_gather,
+                                 hipStream_t s, const Timer* t, int* blocks_used);
 hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s);
 hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s);
 
@@ -151,6 +154,7 @@ struct BatchBegin {
     int n;
     float g[kMaxBatch];
     int hist[kMaxBatch];
+    int gather[kMaxBatch];  // m = 256 carry form: stage does not hold the first iteration's gather
 };
 hipError_t batch_frame_prepare(int M, int phase, int* blocks_per_cu);
 hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* items, int n, int grid,
