@@ -176,15 +176,15 @@ def batched_form(iters: int = 20) -> dict:
             "speedup": round(ms_p / ms_b, 3)}
 
 
-# HBM bytes per launch of the dominant kernels from rocprofv3 counters
-# (FETCH_SIZE and WRITE_SIZE, each scaled by the ratio the same counter gives
-# for a copy of known size; see profiles/).  None until measured on the
-# kernel as it stands.
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch of the large-frame kernels from rocprofv3 counters
+# (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the ratios the same counters give
+# for a 1 GiB device copy), taken on the kernels as they stand; the summary
+# with its commands is profiles/raar_carry_form_2048obj_2025x256_kernels.txt.
+MEASURED_TRAFFIC = {("cols", 2): 4_778_900_000, ("merge", 2): 2_219_100_000}
 
 
-def traffic_for(kernel: str):
-    return MEASURED_TRAFFIC.get(kernel)
+def traffic_for(kernel: str, form: int):
+    return MEASURED_TRAFFIC.get((kernel, form))
 
 
 def copy_calibration(nbytes: int = 1 << 30) -> None:
@@ -329,7 +329,7 @@ def main() -> int:
         dom = max((k for k in per if k in B), key=lambda k: per[k]["ms_mean"])
         ach = B[dom] / (per[dom]["ms_mean"] / 1e3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom),
+                           "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom, form),
                            "kernel": kernel_names(s.m, form).get(dom, dom), "alg_bytes_per_launch": B[dom],
                            "launch_ms": per[dom]["ms_mean"]}
     del plan
