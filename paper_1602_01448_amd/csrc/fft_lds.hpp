@@ -157,6 +157,7 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ lds, const float2
     // would hold hundreds of addresses live in registers).
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
+    tid &= 1023;  // non-negative: index divisions by powers of two stay shifts
     float2 v[PER][R];
 #pragma unroll
     for (int p = 0; p < PER; ++p) {

@@ -74,10 +74,12 @@ __device__ __forceinline__ int wrap(int v, int n) { return v >= n ? v - n : v; }
 // Thread index the compiler cannot treat as loop-invariant: per-item address
 // arithmetic stays inside the item instead of being hoisted (and held live)
 // across the item loop.
+// The mask (blocks have at most 1024 threads) tells the compiler that the
+// value is non-negative, so index divisions by powers of two stay shifts.
 __device__ __forceinline__ int opaque_tid() {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
-    return t;
+    return t & 1023;
 }
 
 // Memory access through a uniform base pointer plus a 32-bit element offset
@@ -174,12 +176,17 @@ struct ModOp {
             if (ok) out_f[i] = cabs2(v);
         }
     }
-    // P_a on one value: a sgn(v), sgn(0) := 1; GRAD keeps v - a sgn(v)
+    // P_a on one value: a sgn(v), sgn(0) := 1; GRAD keeps v - a sgn(v).
+    // One reciprocal square root gives both v / |v| and |v| (to an ulp or so).
     __device__ __forceinline__ float2 modulus(float2 v, float av, bool ok) {
         const float n2 = cabs2(v);
-        const float mag = sqrtf(n2);
         float2 s = make_float2(1.f, 0.f);
-        if (n2 > 0.f) s = cscale(v, 1.0f / mag);
+        float mag = 0.f;
+        if (n2 > 0.f) {
+            const float r = rsqrtf(n2);
+            s = cscale(v, r);
+            mag = n2 * r;
+        }
         const float d = mag - av;
         if (ok) resid += d * d;
         const float2 p = cscale(s, av);
@@ -1056,9 +1063,11 @@ __device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b,
     const int sr = SH == 2 ? (line & 1) : 0;
     const float g = A.beta;
     float2 ww[16];
+    // an absent line (record frame -1) has row 0 and x 0: its values stay in
+    // bounds and are never stored
     auto loadw = [&](const int4& rec) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) ww[r] = rec.x >= 0 ? ldc(A.w, (unsigned)rec.y * M + j + 16 * r) : make_float2(0.f, 0.f);
+        for (int r = 0; r < 16; ++r) ww[r] = ldc(A.w, (unsigned)rec.y * M + j + 16 * r);
     };
     int4 cur = strip_my_record(S, b, e, line);
     loadw(cur);
@@ -1066,12 +1075,9 @@ __device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b,
         float2 v[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            v[r] = make_float2(0.f, 0.f);
-            if (cur.x >= 0) {
-                int gx = cur.z + j + 16 * r;
-                if (gx >= nx) gx -= nx;
-                v[r] = gather_z(ww[r], psi_rows[sr * nx + gx], g);
-            }
+            int gx = cur.z + j + 16 * r;
+            if (gx >= nx) gx -= nx;
+            v[r] = gather_z(ww[r], psi_rows[sr * nx + gx], g);
         }
         line_stage1<1>(v, lds, line, j);
         const int4 nxt = strip_my_record(S, i + FPB, e, line);
@@ -1103,10 +1109,12 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
     for (int r = 1; r < 16; ++r) tw[r - 1] = twl[j * r];
     const bool owned = !A.periodic || (nx & (M - 1)) == 0;
     float2 v[16];
+    // an absent line (record frame -1, row 0, x 0) reads frame 0 row 0: in
+    // bounds, and its transform is never summed
     auto load_line = [&](const int4& rec) {
         const float2* src = A.stage + (size_t)(rec.x < 0 ? 0 : rec.x) * MM + (size_t)rec.y * M + j;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = rec.x >= 0 ? src[16 * r] : make_float2(0.f, 0.f);
+        for (int r = 0; r < 16; ++r) v[r] = src[16 * r];
     };
     int4 mine = strip_my_record(S, b, e, line);
     int4 cur = strip_records(S, b, e, lane);
@@ -1120,11 +1128,8 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
         if (owned) {
 #pragma unroll
             for (int l = 0; l < LINES; ++l) {
-                wv[l] = make_float2(0.f, 0.f);
-                if (__builtin_amdgcn_readlane(cur.x, l) >= 0) {
-                    const unsigned x = (unsigned)(tid - __builtin_amdgcn_readlane(cur.z, l)) & (M - 1);
-                    wv[l] = ldc(A.w, (unsigned)__builtin_amdgcn_readlane(cur.y, l) * M + x);
-                }
+                const unsigned x = (unsigned)(tid - __builtin_amdgcn_readlane(cur.z, l)) & (M - 1);
+                wv[l] = ldc(A.w, (unsigned)__builtin_amdgcn_readlane(cur.y, l) * M + x);
             }
         }
         line_sync();
