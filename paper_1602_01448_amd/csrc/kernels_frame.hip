@@ -82,6 +82,15 @@ __device__ __forceinline__ int opaque_tid() {
     return t & 1023;
 }
 
+// The threads of a transform line lie in one wavefront, whose LDS accesses
+// are performed in program order: exchanges inside a line only need the
+// compiler to keep that order.
+__device__ __forceinline__ void line_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Memory access through a uniform base pointer plus a 32-bit element offset
 // (the compiler then addresses with a scalar base and one vector offset).
 __device__ __forceinline__ const char* byte_at(const void* p, unsigned elem, unsigned size) {
@@ -367,6 +376,290 @@ __global__ void __launch_bounds__(FG<M>::NT) fg_kernel(FrameArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// m = 128, Fourier-domain carry: U = F u is kept per frame, so an iteration
+// is Z = U + F(g w_g T psi), Y = a sgn Z, U' = beta Z + (1 - 2 beta) Y and
+// v = conj(w) F*(2Y - Z) -- no frame-space iterate has to survive the
+// transforms.  One 1024-thread workgroup per CU loops over frames.  A
+// 128-point line lives in 8 threads (16 elements each): a radix-8 and a
+// radix-16 Stockham stage in registers, the exchange between them inside the
+// line's wavefront.  Rows -> columns -> rows go through one 128 KiB LDS frame
+// buffer, two workgroup barriers per frame.  Plan A (radix 8, then 16) starts
+// from element pairs 2t + h + 16 r, plan B (16, then 8) ends on them, so every
+// global access moves two adjacent elements; U and a second copy of the
+// amplitudes are stored transposed per frame ([kx][ky]) for the same reason
+// on the column side.
+// ---------------------------------------------------------------------------
+static const Timer kNoTimer{};
+
+// LDS position of frame element (y, x): XOR swizzle of the low five bits of
+// x, chosen so that the row-thread and column-thread patterns below (8 lines
+// of 8 threads per wavefront) hit distinct banks, except plan B's second-stage
+// column reads (two-way).
+__device__ __forceinline__ int sw128(int y, int x) {
+    const int b0 = (y ^ (y >> 2)) & 1, b3 = (y ^ (y >> 4)) & 1, b4 = ((y >> 1) ^ (y >> 5)) & 1;
+    return y * 128 + (x ^ (x >> 4) ^ b0 ^ (b3 << 3) ^ (b4 << 4));
+}
+
+// A copy of an index the compiler must treat as unknown (keeps address
+// arithmetic local to the stage that uses it).
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x & 1023;
+}
+
+template <bool COL>
+__device__ __forceinline__ int l128_at(int line, int e) {
+    return COL ? sw128(e, line) : sw128(line, e);
+}
+
+// Plan A: held v[2 r + h] = element 2t + h + 16 r.  Radix-8 butterflies
+// 2t, 2t + 1 -> LDS elements 8 j + q; radix-16 butterfly t on elements
+// t + 8 r with twiddles W^(t r).  Ends with v[q] = element t + 8 q.
+template <int DIR, bool COL>
+__device__ __forceinline__ void l128_planA(float2 (&v)[16], float2* lds, const float2* twl, int line, int t) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        float2 b[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) b[r] = v[2 * r + h];
+        dft<8, DIR>(b);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) lds[l128_at<COL>(line, 8 * (2 * t + h) + q)] = b[q];
+    }
+    line_sync();
+    line = opaque(line);
+    t = opaque(t);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = lds[l128_at<COL>(line, t + 8 * r)];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) {
+        float2 w = twl[t * r];
+        if constexpr (DIR < 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+    }
+    dft<16, DIR>(v);
+}
+
+// Plan B: held v[r] = element t + 8 r.  Radix-16 butterfly t -> LDS
+// elements 16 t + q; radix-8 butterflies k = 2t, 2t + 1 on elements k + 16 r
+// with twiddles W^(k r).  Ends with v[2 q + h] = element 2t + h + 16 q.
+template <int DIR, bool COL>
+__device__ __forceinline__ void l128_planB(float2 (&v)[16], float2* lds, const float2* twl, int line, int t) {
+    dft<16, DIR>(v);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lds[l128_at<COL>(line, 16 * t + q)] = v[q];
+    line_sync();
+    line = opaque(line);
+    t = opaque(t);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = 2 * t + h;
+        float2 b[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) b[r] = lds[l128_at<COL>(line, k + 16 * r)];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {
+            float2 w = twl[k * r];
+            if constexpr (DIR < 0) w.y = -w.y;
+            b[r] = cmul(b[r], w);
+        }
+        dft<8, DIR>(b);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[2 * q + h] = b[q];
+    }
+}
+
+enum Fc128Mode : int { FC_RAAR = 0, FC_TO_SPACE = 1, FC_TO_CARRY = 2 };
+
+// One frame f.  RAAR: the carry-form step (reads A.u = U transposed, A.at =
+// amplitudes transposed, gathers psi; writes U' and v = conj(w) y).
+// FC_TO_SPACE: A.in (U transposed) -> A.out = F* U (natural layout).
+// FC_TO_CARRY: A.in (natural) -> A.out = F A.in (transposed).  Ends with the
+// row threads done with their rows: the next frame's first LDS writes are
+// made by the same threads, so frames need no barrier between them.
+template <int MODE>
+__device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* lds, const float2* twl,
+                                            ModOp<FM_RAAR, 128>& op) {
+    constexpr int M = 128, MM = M * M;
+    const size_t fb = (size_t)f * MM;
+    const float inv_m = 1.0f / M;
+    float2 v[16];
+    if constexpr (MODE != FC_TO_SPACE) {   // rows: load, forward row transform (plan A)
+        const int tid = opaque_tid();
+        const int row = tid >> 3, t = tid & 7;
+        if constexpr (MODE == FC_RAAR) {
+            const int py = A.pos[2 * f], px = A.pos[2 * f + 1];
+            int gy = py + row;
+            if (A.periodic && gy >= A.ny) gy -= A.ny;
+            const unsigned orow = (unsigned)gy * (unsigned)A.nx;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int x = 2 * t + 16 * r;
+                int gx0 = px + x, gx1 = gx0 + 1;
+                if (A.periodic) {
+                    if (gx0 >= A.nx) gx0 -= A.nx;
+                    if (gx1 >= A.nx) gx1 -= A.nx;
+                }
+                float2 w0, w1;
+                ld2(A.w_g, (unsigned)(row * M + x), w0, w1);
+                v[2 * r] = gather_z(w0, ldc(A.psi, orow + gx0), A.g);
+                v[2 * r + 1] = gather_z(w1, ldc(A.psi, orow + gx1), A.g);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) ld2(A.in + fb, (unsigned)(row * M + 2 * t + 16 * r), v[2 * r], v[2 * r + 1]);
+        }
+        l128_planA<1, false>(v, lds, twl, row, t);
+        const int row2 = opaque(row), t2 = opaque(t);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) lds[sw128(row2, t2 + 8 * q)] = v[q];
+        __syncthreads();
+    }
+    {   // columns
+        const int tid = opaque_tid();
+        const int c = 8 * (tid >> 6) + (tid & 7), t = (tid >> 3) & 7;
+        const unsigned cb = (unsigned)(c * M + 2 * t);   // transposed pair (c, 2t + 16 q)
+        if constexpr (MODE == FC_TO_SPACE) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ld2(A.in + fb, cb + 16 * q, v[2 * q], v[2 * q + 1]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = lds[sw128(t + 8 * r, c)];
+            l128_planB<1, true>(v, lds, twl, c, t);
+            if constexpr (MODE == FC_TO_CARRY) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    st2(A.out + fb, cb + 16 * q, cscale(v[2 * q], inv_m), cscale(v[2 * q + 1], inv_m));
+                return;
+            } else {
+                const float b = A.beta, c1 = 1.f - 2.f * A.beta;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    float2 u0, u1;
+                    ld2(A.u + fb, cb + 16 * q, u0, u1);
+                    const float2 av = ldf2(A.at + fb, cb + 16 * q);
+                    const float2 z0 = cadd(u0, cscale(v[2 * q], inv_m)), z1 = cadd(u1, cscale(v[2 * q + 1], inv_m));
+                    const float2 y0 = op.modulus(z0, av.x, true), y1 = op.modulus(z1, av.y, true);
+                    st2(A.u + fb, cb + 16 * q, cadd(cscale(z0, b), cscale(y0, c1)), cadd(cscale(z1, b), cscale(y1, c1)));
+                    v[2 * q] = csub(cscale(y0, 2.f), z0);
+                    v[2 * q + 1] = csub(cscale(y1, 2.f), z1);
+                }
+            }
+        }
+        l128_planA<-1, true>(v, lds, twl, c, t);
+        const int c2 = opaque(c), t2 = opaque(t);   // fresh addresses, not the ones of the first reads
+#pragma unroll
+        for (int q = 0; q < 16; ++q) lds[sw128(t2 + 8 * q, c2)] = v[q];
+    }
+    __syncthreads();
+    {   // rows: inverse row transform (plan B), store
+        const int tid = opaque_tid();
+        const int row = tid >> 3, t = tid & 7;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = lds[sw128(row, t + 8 * r)];
+        l128_planB<-1, false>(v, lds, twl, row, t);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const unsigned o = (unsigned)(row * M + 2 * t + 16 * q);
+            if constexpr (MODE == FC_RAAR) {
+                float2 w0, w1;
+                ld2(A.w, o, w0, w1);
+                st2(A.v + fb, o, cconjmul(w0, cscale(v[2 * q], inv_m)), cconjmul(w1, cscale(v[2 * q + 1], inv_m)));
+            } else {
+                st2(A.out + fb, o, cscale(v[2 * q], inv_m), cscale(v[2 * q + 1], inv_m));
+            }
+        }
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(1024) fc128_kernel(FrameArgs A) {
+    extern __shared__ float2 smem[];
+    __shared__ float red[16];
+    float2* lds = smem;
+    float2* twl = smem + 128 * 128;
+    for (int t = threadIdx.x; t < 128; t += 1024) twl[t] = A.tw[t];
+    __syncthreads();
+    ModOp<FM_RAAR, 128> op{nullptr, nullptr, 0.f};
+    for (int f = blockIdx.x; f < A.K; f += gridDim.x) {
+        fc128_frame<MODE>(A, f, lds, twl, op);
+        if constexpr (MODE != FC_RAAR) __syncthreads();   // conversions start or end on the column side
+    }
+    if constexpr (MODE == FC_RAAR) {
+        const float s = block_sum(op.resid, red);
+        if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
+    }
+}
+
+constexpr size_t kFc128Smem = (size_t)(128 * 128 + 128) * sizeof(float2);
+constexpr int kFc128Groups = 256;
+
+// Workgroup b takes frames b, b + G, b + 2G, ... and writes one residual
+// partial; the batched form runs the same (scan, b) items, so both sum the
+// residual in the same order.
+__host__ __device__ int fc128_groups(int K) { return K < 1 ? 1 : (K < kFc128Groups ? K : kFc128Groups); }
+
+template <int MODE>
+static hipError_t launch_fc128_mode(const FrameArgs& A, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)fc128_kernel<MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFc128Smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(fc128_kernel<MODE>, dim3(fc128_groups(A.K)), dim3(1024), kFc128Smem, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_fc128(const FrameArgs& A, hipStream_t s, const Timer* tp, int* blocks_used) {
+    const Timer& t = tp ? *tp : kNoTimer;
+    t.begin(TC_FRAME);
+    hipError_t e = launch_fc128_mode<FC_RAAR>(A, s);
+    t.end(TC_FRAME);
+    *blocks_used = fc128_groups(A.K);
+    return e;
+}
+
+hipError_t launch_fc128_convert(const FrameArgs& A, int to_space, hipStream_t s) {
+    return to_space ? launch_fc128_mode<FC_TO_SPACE>(A, s) : launch_fc128_mode<FC_TO_CARRY>(A, s);
+}
+
+__global__ void __launch_bounds__(1024) batch_fc128_kernel(const FrameArgs* __restrict__ D,
+                                                           const int2* __restrict__ items, int n) {
+    extern __shared__ float2 smem[];
+    __shared__ float red[16];
+    float2* lds = smem;
+    float2* twl = smem + 128 * 128;
+    if (n <= 0) return;
+    const float2* tw = D[items[0].x].tw;
+    for (int t = threadIdx.x; t < 128; t += 1024) twl[t] = tw[t];
+    __syncthreads();
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        const FrameArgs A = D[w.x];
+        const int G = fc128_groups(A.K);
+        ModOp<FM_RAAR, 128> op{nullptr, nullptr, 0.f};
+        for (int f = w.y; f < A.K; f += G) fc128_frame<FC_RAAR>(A, f, lds, twl, op);
+        const float s = block_sum(op.resid, red);
+        if (threadIdx.x == 0) A.resid[w.y] = s;
+    }
+}
+
+hipError_t batch_fc128_prepare(int* blocks_per_cu) {
+    hipError_t e = hipFuncSetAttribute((const void*)batch_fc128_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kFc128Smem);
+    *blocks_per_cu = 1;
+    return e;
+}
+
+hipError_t launch_batch_fc128(const FrameArgs* D, const int2* items, int n, int grid, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_fc128_kernel, dim3(grid), dim3(1024), kFc128Smem, s, D, items, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // m = 256: three passes through an HBM stage buffer
 // ---------------------------------------------------------------------------
 template <int M, int NT_ = 256>
@@ -580,7 +873,6 @@ __global__ void __launch_bounds__(256) q_kernel(FrameArgs A) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static const Timer kNoTimer{};
 
 template <int M, int MODE>
 static hipError_t launch_fg(const FrameArgs& A, int grid, hipStream_t s, const Timer& t) {
@@ -1011,15 +1303,6 @@ __device__ __forceinline__ int4 strip_records(const StripArgs& S, int i, int e, 
 // The record of the line this thread transforms (line = tid / 16).
 __device__ __forceinline__ int4 strip_my_record(const StripArgs& S, int i, int e, int line) {
     return strip_records(S, i, e, line);
-}
-
-// The 16 threads of a line lie in one wavefront, whose LDS accesses are
-// performed in program order: exchanges inside a line only need the compiler
-// to keep that order.
-__device__ __forceinline__ void line_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // First radix-16 stage of a 256-point line held as v[r] = element j + 16 r;

@@ -21,7 +21,7 @@ inline bool supported_m(int m) { return m == 16 || m == 32 || m == 64 || m == 12
 inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
 
 struct Offsets {
-    size_t tw, pos, tile_ptr, tile_frames, a, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
+    size_t tw, pos, tile_ptr, tile_frames, a, a_t, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
     size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sln, total;
 };
 
@@ -32,7 +32,8 @@ struct sharp_plan_s {
     sharp_options opt{};
     std::vector<int32_t> pos;
     int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
-    int frame_launch = 1;     // m = 256: 1 = three passes + tile merge; 2 = Fourier carry + strip merge
+    int frame_launch = 1;     // 1 = carry in frame space; 2 = carry in the Fourier domain (m = 128: one
+                              // frame kernel + tile merge; m = 256: column pass + strip pass)
     int SH = 0, nstrips = 0;  // strip merge: object rows per strip (0 = form unavailable)
     std::vector<int32_t> strip_ptr, strip_lines;  // strip_lines: 4 ints per (entry, strip row)
     int fft_block = 256;      // m = 256, three launches: threads per pass workgroup
@@ -66,7 +67,8 @@ struct sharp_plan_s {
     const sharp::Timer* tm() const { return timing ? &timer : nullptr; }
 
     template <class T> T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
-    bool carry_form() const { return m == 256 && frame_launch == 2; }
+    bool carry_form() const { return (m == 128 || m == 256) && frame_launch == 2; }
+    bool strip_form() const { return m == 256 && frame_launch == 2; }
     size_t frame_elems() const { return (size_t)K * m * m; }
     size_t obj_elems() const { return (size_t)nx * ny; }
 };

@@ -161,10 +161,10 @@ static void choose_tuning(sharp_plan_s& p) {
     // m = 256: Fourier-domain carry with the merge fused into the last row pass
     // unless asked otherwise; needs a strip of the object in LDS
     p.SH = p.m != 256 || p.nx > 8192 ? 0 : (p.opt.strip_rows == 2 && 2 * p.nx <= 8192) ? 2 : 1;
-    p.frame_launch = p.opt.frame_launch ? p.opt.frame_launch : (p.m == 256 ? 2 : 1);
-    if (p.frame_launch == 2 && !p.SH) p.frame_launch = 1;
-    if (p.m != 256) p.frame_launch = 1;
-    if (p.carry_form()) build_strips(p);
+    p.frame_launch = p.opt.frame_launch ? p.opt.frame_launch : (p.m >= 128 ? 2 : 1);
+    if (p.m == 256 && p.frame_launch == 2 && !p.SH) p.frame_launch = 1;
+    if (p.m < 128) p.frame_launch = 1;
+    if (p.strip_form()) build_strips(p);
 }
 
 static void layout(sharp_plan_s& p) {
@@ -181,6 +181,7 @@ static void layout(sharp_plan_s& p) {
     o.tile_ptr = take((p.ntiles + 1) * sizeof(int32_t));
     o.tile_frames = take(std::max<size_t>(p.tile_frames.size(), 1) * sizeof(int32_t));
     o.a = take(FE * sizeof(float));
+    o.a_t = take(p.m == 128 && p.carry_form() ? FE * sizeof(float) : 0);
     o.u = take(FE * sizeof(float2));
     o.v = take(FE * sizeof(float2));
     o.stage = take(p.m == 256 ? FE * sizeof(float2) : 0);
@@ -320,6 +321,7 @@ FrameArgs sharp::frame_args(const sharp_plan_s& p) {
     A.pos = p.at<int>(p.off.pos);
     A.tw = p.at<float2>(p.off.tw);
     A.a = p.at<float>(p.off.a);
+    A.at = p.at<float>(p.off.a_t);
     A.w_g = p.at<float2>(p.off.w_gat);
     A.w = p.at<float2>(p.off.w_cur);
     A.psi = p.at<float2>(p.off.psi_v);
@@ -361,6 +363,7 @@ MergeArgs sharp::merge_args(const sharp_plan_s& p) {
 }
 
 int sharp::resid_blocks_default(const sharp_plan_s& p) {
+    if (p.m == 128 && p.carry_form()) return fc128_groups(p.K);
     return p.m == 256 ? p.K * 16 : (p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
 }
 
@@ -383,7 +386,8 @@ extern "C" int sharp_set_data(sharp_plan p, const float* d_I) {
     if (!p->has_ws) return SHARP_ERR_NOT_READY;
     int blocks = 0;
     HIPCHK(launch_set_data(d_I, p->at<float>(p->off.a), p->frame_elems(), p->at<float>(p->off.resid),
-                           p->at<int>(p->off.flag), p->stream, &blocks, p->m == 256));
+                           p->at<int>(p->off.flag), p->stream, &blocks, p->m == 256,
+                           p->m == 128 && p->carry_form() ? p->at<float>(p->off.a_t) : nullptr));
     HIPCHK(launch_reduce(p->at<float>(p->off.resid), blocks, p->at<float>(p->off.scal), p->stream));
     p->has_data = true;
     return SHARP_OK;
@@ -443,12 +447,21 @@ extern "C" int sharp_set_object(sharp_plan p, const void* d_psi) {
 // ---------------------------------------------------------------------------
 // iteration
 // ---------------------------------------------------------------------------
-// Fourier-domain carry (m = 256 merged form) -> frame space, into dst [K][m][m]
+// Fourier-domain carry -> frame space (u = F* U), into dst [K][m][m]
 static hipError_t carry_to_space(sharp_plan_s& p, float2* dst) {
     FrameArgs A = frame_args(p);
     A.in = p.at<float2>(p.off.u);
     A.out = dst;
+    if (p.m == 128) return launch_fc128_convert(A, 1, p.stream);
     return launch_carry_to_space(A, p.stream);
+}
+// frame space -> Fourier-domain carry (U = F u)
+static hipError_t space_to_carry(sharp_plan_s& p, const float2* src) {
+    FrameArgs A = frame_args(p);
+    A.in = src;
+    A.out = p.at<float2>(p.off.u);
+    if (p.m == 128) return launch_fc128_convert(A, 0, p.stream);
+    return launch_space_to_carry(A, p.stream);
 }
 static int one_iteration(sharp_plan_s& p, float beta) {
     hipStream_t s = p.stream;
@@ -459,7 +472,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     A.beta = beta;
     int blocks = 0;
     const Timer* t = p.tm();
-    if (p.carry_form()) {
+    if (p.strip_form()) {
         // frame phase and merge in one sequence; psi_v is final afterwards.  The
         // strip pass also prepares the next iteration's gather unless a probe
         // update (which reuses the stage buffer) follows.
@@ -467,6 +480,8 @@ static int one_iteration(sharp_plan_s& p, float beta) {
                                      p.at<float>(p.off.Dinv), p.at<float2>(p.off.psi_v), !p.stage_gather,
                                      !probe_due, s, t, &blocks));
         p.stage_gather = !probe_due;
+    } else if (p.carry_form()) {
+        HIPCHK(launch_fc128(A, s, t, &blocks));
     } else if (p.m == 256) {
         HIPCHK(launch_raar_mp256(A, p.fft_block, s, t, &blocks));
     } else {
@@ -485,6 +500,11 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     MergeArgs Mg = merge_args(p);
     const float2* u_space = p.at<float2>(p.off.u);
     if (p.carry_form()) {
+        if (!p.strip_form()) {  // m = 128: the frame kernel wrote v; tile merge
+            if (t) t->begin(TC_MERGE);
+            HIPCHK(launch_merge(MK_V, Mg, p.ntiles, s));
+            if (t) t->end(TC_MERGE);
+        }
         if (probe_due) {
             // psi^(l) and the probe update need the carry in frame space
             if (t) t->begin(TC_PROBE);
@@ -740,10 +760,7 @@ extern "C" int sharp_set_state(sharp_plan p, const void* d_state) {
         return SHARP_ERR_INVALID_ARG;
     const size_t MM = (size_t)p->m * p->m;
     if (p->carry_form()) {
-        FrameArgs A = frame_args(*p);
-        A.in = (const float2*)(d + L.u);
-        A.out = p->at<float2>(p->off.u);
-        HIPCHK(launch_space_to_carry(A, s));
+        HIPCHK(space_to_carry(*p, (const float2*)(d + L.u)));
     } else {
         HIPCHK(launch_copy(p->ws + p->off.u, d + L.u, p->frame_elems() * sizeof(float2), s));
     }
@@ -781,7 +798,7 @@ extern "C" int sharp_get_plan_info(sharp_plan p, sharp_plan_info* info) {
     info->grad_groups = p->grad_groups;
     info->frame_launch = p->frame_launch;
     info->fft_block = p->fft_block;
-    info->strip_rows = p->carry_form() ? p->SH : 0;
+    info->strip_rows = p->strip_form() ? p->SH : 0;
     info->csr_nnz = (long long)p->tile_frames.size();
     info->iteration = p->iter;
     return SHARP_OK;

@@ -43,9 +43,10 @@ struct sharp_batch_s {
     std::vector<int4> merge_items[3];     // per merge-tile class
     std::vector<int2> finish_items[3];
     std::vector<int2> carry_items[3];     // m = 256 Fourier-carry form: rows, columns, strips
+    std::vector<int2> fc_items;           // m = 128 Fourier-carry form: (scan, frame group)
     size_t carry_smem = 0;                // LDS of the strip phase (widest object)
     struct {
-        size_t fargs, margs, eps, sargs, fitems[5], mitems[3], fin[3], citems[3], total;
+        size_t fargs, margs, eps, sargs, fitems[5], mitems[3], fin[3], citems[3], fcitems, total;
     } off{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -54,6 +55,7 @@ struct sharp_batch_s {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int grid_frame[5][3] = {};
     int grid_carry[3] = {};
+    int grid_fc = 1;
     int grid_merge = 0;
     std::map<std::pair<int, float>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 
@@ -87,7 +89,7 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         for (int s = 0; s < nplans; ++s) {
             sharp_plan_s* p = plans[s];
             b->plans.push_back(p);
-            if (p->carry_form()) {
+            if (p->strip_form()) {
                 for (int it = 0; it < p->K * 16; ++it) {
                     b->carry_items[0].push_back(make_int2(s, it));
                     b->carry_items[1].push_back(make_int2(s, it));
@@ -96,9 +98,13 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
                 b->carry_smem = std::max(b->carry_smem, strip_smem_bytes(p->SH, p->nx));
                 continue;  // merged in the strip phase, no tile merge
             }
-            const int mc = m_class(p->m);
             const int items = resid_blocks_default(*p);  // frame groups (m <= 128) or row blocks (m = 256)
-            for (int it = 0; it < items; ++it) b->frame_items[mc].push_back(make_int2(s, it));
+            if (p->carry_form()) {  // m = 128, Fourier-domain carry: (scan, frame group) items
+                for (int it = 0; it < items; ++it) b->fc_items.push_back(make_int2(s, it));
+            } else {
+                const int mc = m_class(p->m);
+                for (int it = 0; it < items; ++it) b->frame_items[mc].push_back(make_int2(s, it));
+            }
             const int tc = t_class(p->T);
             for (int t = 0; t < p->ntiles; ++t)
                 for (int c = 0; c < p->split; ++c) b->merge_items[tc].push_back(make_int4(s, t, c, 0));
@@ -116,6 +122,7 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         b->off.eps = take(nplans * sizeof(EpsDesc));
         b->off.sargs = take(nplans * sizeof(StripArgs));
         for (int c = 0; c < 3; ++c) b->off.citems[c] = take(b->carry_items[c].size() * sizeof(int2));
+        b->off.fcitems = take(b->fc_items.size() * sizeof(int2));
         for (int c = 0; c < 5; ++c) b->off.fitems[c] = take(b->frame_items[c].size() * sizeof(int2));
         for (int c = 0; c < 3; ++c) {
             b->off.mitems[c] = take(b->merge_items[c].size() * sizeof(int4));
@@ -182,6 +189,9 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         if (!b->carry_items[c].empty())
             HIPCHK(hipMemcpyAsync(b->ws + b->off.citems[c], b->carry_items[c].data(),
                                   b->carry_items[c].size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    if (!b->fc_items.empty())
+        HIPCHK(hipMemcpyAsync(b->ws + b->off.fcitems, b->fc_items.data(), b->fc_items.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, st));
     for (int c = 0; c < 5; ++c)
         if (!b->frame_items[c].empty())
             HIPCHK(hipMemcpyAsync(b->ws + b->off.fitems[c], b->frame_items[c].data(),
@@ -211,6 +221,11 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         if (!b->carry_items[ph].empty()) HIPCHK(batch_carry_prepare(ph, smem, &per));
         b->grid_carry[ph] = std::max(1, per * cus);
     }
+    if (!b->fc_items.empty()) {
+        int per = 1;
+        HIPCHK(batch_fc128_prepare(&per));
+        b->grid_fc = std::max(1, per * cus);
+    }
     b->grid_merge = 8 * cus;
     return SHARP_OK;
 }
@@ -227,6 +242,10 @@ static int enqueue_iterations(sharp_batch_s& b, int n, float beta, hipStream_t s
             const int2* items = b.at<int2>(b.off.fitems[c]);
             for (int ph = 0; ph < (kM[c] == 256 ? 3 : 1); ++ph)
                 HIPCHK(launch_batch_frame(kM[c], ph, D, items, cnt, std::min(cnt, b.grid_frame[c][ph]), s));
+        }
+        if (!b.fc_items.empty()) {
+            const int cnt = (int)b.fc_items.size();
+            HIPCHK(launch_batch_fc128(D, b.at<int2>(b.off.fcitems), cnt, std::min(cnt, b.grid_fc), s));
         }
         for (int ph = l == 0 ? 0 : 1; ph < 2; ++ph) {  // later gathers come from the strip phase
             const int cnt = (int)b.carry_items[ph].size();
@@ -292,7 +311,7 @@ extern "C" int sharp_batch_raar_iterate(sharp_batch b, int n, float beta) {
         p->hist_count += n;
         p->g = beta;
         p->last_probe_updated = false;
-        p->stage_gather = p->carry_form();
+        p->stage_gather = p->strip_form();
     }
     return SHARP_OK;
 }

@@ -47,6 +47,7 @@ struct FrameArgs {
     const float2* __restrict__ tw;      // [M] e^{2 pi i t / M}
     const float* __restrict__ a;        // [K][M][M] amplitudes
     const float2* __restrict__ w_g;     // gather probe
+    const float* __restrict__ at;       // m = 128 carry form: amplitudes, per frame transposed
     const float2* __restrict__ w;       // current probe
     const float2* __restrict__ psi;     // gathered object (psi_v, or psi for GRAD/SIM/Q)
     const float2* __restrict__ in;      // input frames (PA/F/FINV)
@@ -104,7 +105,7 @@ hipError_t launch_gw_finish(int M, int slots, const float2* part, float2* gw, hi
 // launchers (kernels_merge.hip)
 hipError_t launch_merge(int kind, const MergeArgs& a, int tiles, hipStream_t s);
 hipError_t launch_set_data(const float* I, float* a, size_t n, float* partials, int* flag,
-                           hipStream_t s, int* blocks_used, int blocked256);
+                           hipStream_t s, int* blocks_used, int blocked256, float* a_t128);
 hipError_t launch_reduce(const float* partials, int n, float* out, hipStream_t s);
 hipError_t launch_eps(const float* partials, int n, const float* norm_a2, float* hist, int idx,
                       int* flag, hipStream_t s);
@@ -130,6 +131,13 @@ struct StripArgs {
                                      // frame rows (w * T psi_v scaled by beta) in the stage buffer
 };
 size_t carry_phase_smem();
+// m = 128 with the RAAR carry kept in the Fourier domain
+__host__ __device__ int fc128_groups(int K);
+hipError_t launch_fc128(const FrameArgs& A, hipStream_t s, const Timer* t, int* blocks_used);
+// to_space: A.out = F* A.in (A.in transposed carry); else A.out (transposed) = F A.in
+hipError_t launch_fc128_convert(const FrameArgs& A, int to_space, hipStream_t s);
+hipError_t batch_fc128_prepare(int* blocks_per_cu);
+hipError_t launch_batch_fc128(const FrameArgs* D, const int2* items, int n, int grid, hipStream_t s);
 hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu);
 hipError_t launch_batch_carry(int phase, const FrameArgs* D, const StripArgs* SD, const int2* items, int n, int grid,
                               size_t smem, hipStream_t s);

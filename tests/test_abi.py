@@ -97,6 +97,20 @@ def test_large_frame_form_selection(L, n, kw, form, rows):
     L.sharp_plan_destroy(h)
 
 
+@pytest.mark.parametrize("m,kw,form", [(128, {}, 2), (128, {"frame_launch": 1}, 1), (64, {}, 1),
+                                       (64, {"frame_launch": 2}, 1), (32, {}, 1)])
+def test_small_frame_form_selection(L, m, kw, form):
+    """m = 128 keeps the carry in the Fourier domain by default; smaller
+    frames always keep it in frame space."""
+    from paper_1602_01448_amd._lib import SharpPlanInfo
+    st, h = _create(L, 300, m, [(0, 0), (300 - m, 300 - m)], **kw)
+    assert st == 0
+    info = SharpPlanInfo()
+    assert L.sharp_get_plan_info(h, ctypes.byref(info)) == 0
+    assert (info.frame_launch, info.strip_rows) == (form, 0)
+    L.sharp_plan_destroy(h)
+
+
 def test_calls_before_workspace_are_not_ready(L):
     st, h = _create(L, 64, 32, [(0, 0), (8, 8)])
     assert st == 0

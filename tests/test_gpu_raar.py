@@ -313,6 +313,58 @@ def test_large_frame_prepared_gather_equals_gather_pass(periodic):
     assert np.max(np.abs(plans[0].metrics() / plans[1].metrics() - 1)) < 2e-6
 
 
+def _scan128(seed, periodic, probe_every=0):
+    rng = np.random.default_rng(seed)
+    n, m = (360, 128) if periodic else (352, 128)
+    if periodic:
+        pos = np.array([(40 * j + 11, 40 * k + 3) for j in range(9) for k in range(9)], np.int32) % n
+    else:
+        pos = gen.raster_positions(6, 44.8, n, m, jitter=2, rng=rng)
+    return gen.Scan("f128", n, m, pos, gen.random_object(rng, n, n), gen.gaussian_probe(m, 24.0),
+                    rng.uniform(0, 1, (n, n)).astype(complex), None, 0.75, 4, probe_every, 1, periodic, None)
+
+
+@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_frame128_forms_match_oracle(form, periodic):
+    """Both m = 128 forms (carry in frame space; carry in the Fourier domain
+    with register-resident line transforms) against the oracle, with and
+    without periodic wrap (object side 360 is not a multiple of 128)."""
+    s = _scan128(40 + form, periodic)
+    p, got, ref, D = _run_both(s, 4, frame_launch=form)
+    assert p.info()["frame_launch"] == form
+    assert dweighted(got["psi"], ref["psi"], D) < 1e-4
+    assert np.max(np.abs(got["eps"] - ref["eps_a"]) / ref["eps_a"]) < 1e-4
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_frame128_probe_refinement(form):
+    s = _scan128(45, False, probe_every=1)
+    p, got, ref, D = _run_both(s, 3, known_probe=False, frame_launch=form)
+    assert rel(got["w"], ref["w"]) < 1e-4
+    assert dweighted(got["psi"], ref["psi"], D) < 1e-4
+
+
+def test_frame128_checkpoint_resume():
+    """Fourier-domain carry at m = 128: the state holds the carry in frame
+    space; resuming continues the run to rounding."""
+    s = _scan128(47, False)
+    I, _ = _data(s)
+    from paper_1602_01448_amd import Plan
+    def fresh():
+        q = Plan(s.n, s.n, s.m, s.positions)
+        return q.set_data(to_dev(I)).set_probe(to_dev(c64(s.probe))).set_object(to_dev(c64(s.psi0)))
+    full = fresh().raar(6, 0.75)
+    half = fresh().raar(3, 0.75)
+    st = half.state().clone()
+    r = Plan(s.n, s.n, s.m, s.positions)
+    r.set_data(to_dev(I)).load_state(st).raar(3, 0.75)
+    D = O.illumination_density(s.probe, s.positions, (s.n, s.n))
+    assert full.info()["frame_launch"] == 2
+    assert dweighted(to_host(r.object()), to_host(full.object()), D) < 1e-5
+    assert np.array_equal(r.metrics()[:3], full.metrics()[:3])
+
+
 def test_periodic_convergence_to_known_object():
     """Noiseless periodic scan, known probe, random start: like the oracle's
     convergence pin, the GPU run drives eps_0 (Eq. (solutionmetric)) down to the
