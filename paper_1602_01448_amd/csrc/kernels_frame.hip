@@ -469,17 +469,23 @@ __device__ __forceinline__ void l128_planB(float2 (&v)[16], float2* lds, const f
     }
 }
 
-enum Fc128Mode : int { FC_RAAR = 0, FC_TO_SPACE = 1, FC_TO_CARRY = 2 };
+enum Fc128Mode : int { FC_RAAR = 0, FC_TO_SPACE = 1, FC_TO_CARRY = 2, FC_GRAD = 3 };
+
+template <int MODE>
+using Fc128Op = ModOp<MODE == FC_GRAD ? FM_GRAD : FM_RAAR, 128>;
 
 // One frame f.  RAAR: the carry-form step (reads A.u = U transposed, A.at =
 // amplitudes transposed, gathers psi; writes U' and v = conj(w) y).
 // FC_TO_SPACE: A.in (U transposed) -> A.out = F* U (natural layout).
-// FC_TO_CARRY: A.in (natural) -> A.out = F A.in (transposed).  Ends with the
-// row threads done with their rows: the next frame's first LDS writes are
-// made by the same threads, so frames need no barrier between them.
+// FC_TO_CARRY: A.in (natural) -> A.out = F A.in (transposed).  FC_GRAD:
+// z = w T psi, r = 2 F*(Z - a sgn Z); writes v = conj(w) r and adds
+// conj(T psi) r to the workgroup's probe-gradient partial (its own slot of
+// A.gw_part; each thread updates the same 16 pixels every frame).  Ends with
+// the row threads done with their rows: the next frame's first LDS writes
+// are made by the same threads, so frames need no barrier between them.
 template <int MODE>
 __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* lds, const float2* twl,
-                                            ModOp<FM_RAAR, 128>& op) {
+                                            Fc128Op<MODE>& op) {
     constexpr int M = 128, MM = M * M;
     const size_t fb = (size_t)f * MM;
     const float inv_m = 1.0f / M;
@@ -487,7 +493,8 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
     if constexpr (MODE != FC_TO_SPACE) {   // rows: load, forward row transform (plan A)
         const int tid = opaque_tid();
         const int row = tid >> 3, t = tid & 7;
-        if constexpr (MODE == FC_RAAR) {
+        if constexpr (MODE == FC_RAAR || MODE == FC_GRAD) {
+            const float g = MODE == FC_GRAD ? 1.f : A.g;
             const int py = A.pos[2 * f], px = A.pos[2 * f + 1];
             int gy = py + row;
             if (A.periodic && gy >= A.ny) gy -= A.ny;
@@ -502,8 +509,8 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
                 }
                 float2 w0, w1;
                 ld2(A.w_g, (unsigned)(row * M + x), w0, w1);
-                v[2 * r] = gather_z(w0, ldc(A.psi, orow + gx0), A.g);
-                v[2 * r + 1] = gather_z(w1, ldc(A.psi, orow + gx1), A.g);
+                v[2 * r] = gather_z(w0, ldc(A.psi, orow + gx0), g);
+                v[2 * r + 1] = gather_z(w1, ldc(A.psi, orow + gx1), g);
             }
         } else {
 #pragma unroll
@@ -531,6 +538,13 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
                 for (int q = 0; q < 8; ++q)
                     st2(A.out + fb, cb + 16 * q, cscale(v[2 * q], inv_m), cscale(v[2 * q + 1], inv_m));
                 return;
+            } else if constexpr (MODE == FC_GRAD) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float2 av = ldf2(A.at + fb, cb + 16 * q);
+                    v[2 * q] = cscale(op.modulus(cscale(v[2 * q], inv_m), av.x, true), 2.f);
+                    v[2 * q + 1] = cscale(op.modulus(cscale(v[2 * q + 1], inv_m), av.y, true), 2.f);
+                }
             } else {
                 const float b = A.beta, c1 = 1.f - 2.f * A.beta;
 #pragma unroll
@@ -565,6 +579,24 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
                 float2 w0, w1;
                 ld2(A.w, o, w0, w1);
                 st2(A.v + fb, o, cconjmul(w0, cscale(v[2 * q], inv_m)), cconjmul(w1, cscale(v[2 * q + 1], inv_m)));
+            } else if constexpr (MODE == FC_GRAD) {
+                // T psi is gathered again (the object reads hit the caches)
+                const int py = A.pos[2 * f], px = A.pos[2 * f + 1];
+                int gy = py + row, gx0 = px + 2 * t + 16 * q, gx1 = gx0 + 1;
+                if (A.periodic) {
+                    if (gy >= A.ny) gy -= A.ny;
+                    if (gx0 >= A.nx) gx0 -= A.nx;
+                    if (gx1 >= A.nx) gx1 -= A.nx;
+                }
+                const unsigned orow = (unsigned)gy * (unsigned)A.nx;
+                float2 w0, w1;
+                ld2(A.w, o, w0, w1);
+                const float2 r0 = cscale(v[2 * q], inv_m), r1 = cscale(v[2 * q + 1], inv_m);
+                st2(A.v + fb, o, cconjmul(w0, r0), cconjmul(w1, r1));
+                float2* gp = A.gw_part + (size_t)blockIdx.x * MM;
+                float2 g0 = make_float2(0.f, 0.f), g1 = g0;
+                if (f != (int)blockIdx.x) ld2(gp, o, g0, g1);   // not this workgroup's first frame
+                st2(gp, o, cadd(g0, cconjmul(ldc(A.psi, orow + gx0), r0)), cadd(g1, cconjmul(ldc(A.psi, orow + gx1), r1)));
             } else {
                 st2(A.out + fb, o, cscale(v[2 * q], inv_m), cscale(v[2 * q + 1], inv_m));
             }
@@ -580,12 +612,13 @@ __global__ void __launch_bounds__(1024) fc128_kernel(FrameArgs A) {
     float2* twl = smem + 128 * 128;
     for (int t = threadIdx.x; t < 128; t += 1024) twl[t] = A.tw[t];
     __syncthreads();
-    ModOp<FM_RAAR, 128> op{nullptr, nullptr, 0.f};
+    Fc128Op<MODE> op{nullptr, nullptr, 0.f};
     for (int f = blockIdx.x; f < A.K; f += gridDim.x) {
         fc128_frame<MODE>(A, f, lds, twl, op);
-        if constexpr (MODE != FC_RAAR) __syncthreads();   // conversions start or end on the column side
+        if constexpr (MODE == FC_TO_SPACE || MODE == FC_TO_CARRY)
+            __syncthreads();   // conversions start or end on the column side
     }
-    if constexpr (MODE == FC_RAAR) {
+    if constexpr (MODE == FC_RAAR || MODE == FC_GRAD) {
         const float s = block_sum(op.resid, red);
         if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
     }
@@ -625,6 +658,23 @@ hipError_t launch_fc128_convert(const FrameArgs& A, int to_space, hipStream_t s)
     return to_space ? launch_fc128_mode<FC_TO_SPACE>(A, s) : launch_fc128_mode<FC_TO_CARRY>(A, s);
 }
 
+hipError_t launch_fc128_grad(const FrameArgs& A, int grid, hipStream_t s, const Timer* tp, int* blocks_used) {
+    const Timer& t = tp ? *tp : kNoTimer;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)fc128_kernel<FC_GRAD>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFc128Smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    grid = std::max(1, std::min(grid, A.K));
+    t.begin(TC_FRAME);
+    hipLaunchKernelGGL(fc128_kernel<FC_GRAD>, dim3(grid), dim3(1024), kFc128Smem, s, A);
+    t.end(TC_FRAME);
+    *blocks_used = grid;
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(1024) batch_fc128_kernel(const FrameArgs* __restrict__ D,
                                                            const int2* __restrict__ items, int n) {
     extern __shared__ float2 smem[];
@@ -639,7 +689,7 @@ __global__ void __launch_bounds__(1024) batch_fc128_kernel(const FrameArgs* __re
         const int2 w = items[it];
         const FrameArgs A = D[w.x];
         const int G = fc128_groups(A.K);
-        ModOp<FM_RAAR, 128> op{nullptr, nullptr, 0.f};
+        Fc128Op<FC_RAAR> op{nullptr, nullptr, 0.f};
         for (int f = w.y; f < A.K; f += G) fc128_frame<FC_RAAR>(A, f, lds, twl, op);
         const float s = block_sum(op.resid, red);
         if (threadIdx.x == 0) A.resid[w.y] = s;

@@ -618,7 +618,8 @@ extern "C" int sharp_grad(sharp_plan p, const void* d_psi, const void* d_w, floa
     A.w = (const float2*)d_w;
     A.w_g = (const float2*)d_w;
     int blocks = 0;
-    HIPCHK(launch_frame(FM_GRAD, A, p->grad_groups, s, &blocks, p->tm()));
+    if (p->m == 128 && p->carry_form()) HIPCHK(launch_fc128_grad(A, p->grad_groups, s, p->tm(), &blocks));
+    else HIPCHK(launch_frame(FM_GRAD, A, p->grad_groups, s, &blocks, p->tm()));
     HIPCHK(launch_loss(p->at<float>(p->off.resid), p->m == 256 ? p->K * 16 : blocks, d_loss, p->at<int>(p->off.flag), s));
     if (d_gpsi) {
         MergeArgs Mg = merge_args(*p);

@@ -136,6 +136,8 @@ __host__ __device__ int fc128_groups(int K);
 hipError_t launch_fc128(const FrameArgs& A, hipStream_t s, const Timer* t, int* blocks_used);
 // to_space: A.out = F* A.in (A.in transposed carry); else A.out (transposed) = F A.in
 hipError_t launch_fc128_convert(const FrameArgs& A, int to_space, hipStream_t s);
+// amplitude-loss gradient at m = 128 (carry-form plans, which hold the transposed amplitudes)
+hipError_t launch_fc128_grad(const FrameArgs& A, int grid, hipStream_t s, const Timer* t, int* blocks_used);
 hipError_t batch_fc128_prepare(int* blocks_per_cu);
 hipError_t launch_batch_fc128(const FrameArgs* D, const int2* items, int n, int grid, hipStream_t s);
 hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu);

@@ -63,6 +63,31 @@ def test_gradient_other_sizes(m, K, n):
     assert rel(to_host(gpsi), rpsi) < 1e-5 and rel(to_host(gw), rw) < 1e-5
 
 
+@pytest.mark.parametrize("form,groups,periodic", [(1, 0, False), (2, 0, False), (2, 1, False), (2, 7, False),
+                                                 (2, 0, True)])
+def test_gradient_frame128_forms(form, groups, periodic):
+    """m = 128: frame-space kernel and the register-resident kernel (with its
+    per-workgroup probe-gradient slots, any workgroup count), against the
+    oracle; periodic wrap on an object side that is not a multiple of 128."""
+    from paper_1602_01448_amd import Plan
+    rng = np.random.default_rng(128 + groups)
+    n, m, K = (330, 128, 23)
+    hi = n if periodic else n - m + 1
+    pos = rng.integers(0, hi, size=(K, 2)).astype(np.int32)
+    obj = gen.random_object(rng, n, n)
+    probe = gen.gaussian_probe(m, 24.0)
+    I = O.forward_intensity(obj, probe, pos, periodic).astype(np.float32)
+    psi = c64(obj * (1 + 0.2 * rng.standard_normal((n, n))))
+    w = c64(probe * (1 + 0.1 * rng.standard_normal((m, m))))
+    p = Plan(n, n, m, pos, periodic=periodic, frame_launch=form, grad_groups=groups)
+    p.set_data(to_dev(I))
+    assert p.info()["frame_launch"] == form
+    loss, gpsi, gw = p.grad(to_dev(psi), to_dev(w))
+    L, rpsi, rw = O.amplitude_grad(psi, w, pos, np.sqrt(I.astype(np.float64)), periodic)
+    assert abs(loss.item() - L) / L < 1e-5
+    assert rel(to_host(gpsi), rpsi) < 1e-5 and rel(to_host(gw), rw) < 1e-5
+
+
 def test_autograd_function():
     import torch
     from paper_1602_01448_amd import AmplitudeLoss
