@@ -42,6 +42,16 @@ listed in DESIGN.md):
   R9  Frames are summed in ascending frame index everywhere.
   R10 Gradient of L = sum_i sum_q (|F(w T_i psi)|_q - a_iq)^2 in the complex
       convention g = dL/dRe + i dL/dIm (no 1/2 in L).
+  R14 Probe constraints (algorithm step 7): F is the frame transform of the
+      data (unitary, DC at [0][0]); the Fourier mask m_w multiplies F w; the
+      Fourier amplitudes a_w replace |F w| with sgn(0) := 1; when both are
+      given the mask is used (the box tests for the mask first).
+  R15 Centre-of-mass correction (algorithm step 7): the centroid c of |w|^2
+      over pixel indices (y, x) in 0..m-1 (no wrap); w is rolled circularly by
+      the integer s = floor(m/2 - c + 1/2) per axis, which puts the centroid
+      within half a pixel of the frame centre (m/2, m/2) without
+      interpolation.  The integer is decided in FP32 (as the GPU does): c is
+      formed from FP32 sums.
 """
 from __future__ import annotations
 
@@ -52,6 +62,7 @@ __all__ = [
     "extract", "Q", "Qstar", "illumination_density", "dplus",
     "forward_intensity", "sgn", "P_a", "P_Q",
     "raar_step", "raar", "object_update", "probe_update", "init_probe",
+    "probe_fourier_constraint", "probe_center_shift", "probe_center",
     "eps_a", "eps_Q", "eps_Delta", "eps_0", "amplitude_loss", "amplitude_grad",
 ]
 
@@ -197,6 +208,42 @@ def probe_update(z, psi, positions, periodic=False):
     return out
 
 
+def probe_fourier_constraint(w, mask=None, amplitudes=None):
+    """Algorithm step 7: w := F^{-1}{(F w) m_w} if a mask is given, else
+    w := F^{-1}{sgn(F w) a_w} if Fourier amplitudes are given, else w (R14)."""
+    w = np.asarray(w, dtype=np.complex128)
+    if mask is not None:
+        return idft(dft(w) * np.asarray(mask, dtype=np.float64))
+    if amplitudes is not None:
+        return idft(sgn(dft(w)) * np.asarray(amplitudes, dtype=np.float64))
+    return w
+
+
+def probe_center_shift(w):
+    """Integer roll (sy, sx) that brings the |w|^2 centroid to the frame
+    centre (R15).  Sums in FP32, pixel by pixel in row-major order."""
+    m = w.shape[-1]
+    p = (np.abs(np.asarray(w, dtype=np.complex64)) ** 2).astype(np.float32)
+    tot, sy, sx = np.float32(0), np.float32(0), np.float32(0)
+    for y in range(m):
+        for x in range(m):
+            tot = np.float32(tot + p[y, x])
+            sy = np.float32(sy + np.float32(y) * p[y, x])
+            sx = np.float32(sx + np.float32(x) * p[y, x])
+    if tot <= 0:
+        return 0, 0
+    cy, cx = np.float32(sy / tot), np.float32(sx / tot)
+    half = np.float32(m // 2)
+    return int(np.floor(np.float32(half - cy + np.float32(0.5)))), int(np.floor(np.float32(half - cx + np.float32(0.5))))
+
+
+def probe_center(w):
+    """Centre-of-mass drift correction of algorithm step 7: roll w by
+    probe_center_shift(w)."""
+    sy, sx = probe_center_shift(w)
+    return np.roll(np.asarray(w, dtype=np.complex128), (sy, sx), axis=(0, 1))
+
+
 def init_probe(I):
     """w0 = F^{-1} sqrt(mean_i I_i), centred on the frame (algorithm step 2, R7)."""
     I = np.asarray(I, dtype=np.float64)
@@ -249,7 +296,7 @@ def raar_step(z, beta, proj_a, proj_Q):
 
 def raar(I, positions, shape, m, n_iter, beta=0.75, psi0=None, w0=None,
          probe_every=0, probe_start=1, periodic=False, record_extra=False,
-         rng_init=None):
+         rng_init=None, probe_mask=None, probe_amplitudes=None, probe_center_com=False):
     """The reconstruction sequence of the algorithm box.
 
     Returns a dict with the object psi (step 6 of the last iteration), the
@@ -276,6 +323,9 @@ def raar(I, positions, shape, m, n_iter, beta=0.75, psi0=None, w0=None,
             hist["eps_Delta"].append(eps_Delta(z, z_old, a))
         if probe_every and it >= probe_start and (it - probe_start) % probe_every == 0:
             w = probe_update(z, psi, positions, periodic)                  # step 7
+            w = probe_fourier_constraint(w, probe_mask, probe_amplitudes)
+            if probe_center_com:
+                w = probe_center(w)
             D = illumination_density(w, positions, shape, periodic)
     return {"psi": psi, "w": w, "z": z, **{k: np.array(v) for k, v in hist.items()}}
 
