@@ -133,6 +133,42 @@ def grad_form(reps: int = 10) -> dict:
             "ms_per_call": round(ms, 4), "achieved_alg_GBps": round(alg / (ms / 1e3) / 1e9, 1)}
 
 
+def probe_form(iters: int = 20) -> dict:
+    """Probe refinement every iteration on the probe-retrieval workload (512^2
+    object, 841 frames of 64^2, Poisson 1e6 photons/frame, probe from the
+    data): ms per iteration without constraints and with the Fourier mask plus
+    the centre-of-mass correction of the probe update."""
+    import numpy as np
+    import torch
+
+    from paper_1602_01448_amd import Plan
+    from sharp_data import gen
+
+    dev = torch.device("cuda", 0)
+    s = gen.config_scan(2)
+    obj = torch.from_numpy(s.obj.astype(np.complex64)).to(dev)
+    w = torch.from_numpy(s.probe.astype(np.complex64)).to(dev)
+    f = np.fft.fftfreq(s.m) * s.m
+    mask = torch.from_numpy((np.hypot(f[:, None], f[None, :]) < s.m / 4).astype(np.float32)).to(dev)
+    out = {"workload": f"probe refinement every iteration: object {s.n}x{s.n}, {s.K} frames {s.m}x{s.m}"}
+    for name, center in (("plain", False), ("mask_and_center", True)):
+        plan = Plan(s.n, s.n, s.m, s.positions, probe_every=1, probe_center=center, device=dev)
+        I = plan.simulate(obj, w)
+        plan.set_data(I).init_probe()
+        if center:
+            plan.set_probe_constraint(mask=mask)
+        plan.set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev)).raar(2, s.beta)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        t0.record()
+        plan.raar(iters, s.beta)
+        t1.record()
+        torch.cuda.synchronize(dev)
+        out[f"{name}_ms_per_iteration"] = round(t0.elapsed_time(t1) / iters, 4)
+        del plan
+    return out
+
+
 def batched_form(iters: int = 20) -> dict:
     """32 independent uneven scans (n 256..1024, m in {64,128,256}, 100..1500
     frames), 20 RAAR iterations: batched (one graph launch) vs the same plans
@@ -334,7 +370,8 @@ def main() -> int:
                            "launch_ms": per[dom]["ms_mean"]}
     del plan
     if not args.no_forms:
-        out["forms"] = {"grad": grad_form(), "batched": batched_form(), "paper_fig3": fig3_form()}
+        out["forms"] = {"grad": grad_form(), "batched": batched_form(), "paper_fig3": fig3_form(),
+                        "probe_constraints": probe_form()}
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -78,7 +78,10 @@ typedef struct sharp_options {
                          or 32 rows / columns per workgroup); 0 = 256 */
     int strip_rows;   /* m = 256, form 2: object rows per merge strip, 1 or 2 (0 = default,
                          1); 2 is taken only while 2 nx <= 8192 */
-    int reserved[2];  /* must be zero */
+    int probe_center; /* 1: after every probe update, roll the probe circularly by the integer
+                         that brings the centroid of |w|^2 within half a pixel of (m/2, m/2)
+                         (algorithm box, step 7, centre-of-mass drift correction); 0: off */
+    int reserved[1];  /* must be zero */
 } sharp_options;
 
 /* ------------------------------------------------------------------------
@@ -117,6 +120,18 @@ int sharp_set_probe(sharp_plan plan, const void* d_w);
 /* Initial probe from the data (algorithm box, step 2): w0 = F^{-1} sqrt of
  * the mean frame, shifted by (m/2, m/2) to the frame centre.  Needs data. */
 int sharp_init_probe(sharp_plan plan);
+/* Constraint on every probe update (algorithm box, step 7; Sec. "Phase
+ * retrieval", Fourier-space drifts):
+ *   kind 0: none (default);
+ *   kind 1: Fourier mask m_w:       w := F^{-1}{ (F w) m_w };
+ *   kind 2: Fourier amplitudes a_w: w := F^{-1}{ sgn(F w) a_w }, sgn(0) := 1.
+ * F is the frame transform of the data (unitary, DC at [0][0]).  d_values:
+ * float32 [m][m] device pointer, copied into the workspace (ignored and may
+ * be NULL for kind 0).  It is applied before the centre-of-mass correction
+ * (option probe_center).  Not part of the checkpoint state.
+ * Errors: INVALID_ARG (kind outside 0..2, NULL values), NOT_READY (no
+ * workspace), HIP. */
+int sharp_set_probe_constraint(sharp_plan plan, int kind, const float* d_values);
 /* Start image psi0, complex64 [ny][nx] (copied); sets z^(0) = Q psi0
  * (algorithm box, step 4) and restarts the iteration counter.  Needs probe. */
 int sharp_set_object(sharp_plan plan, const void* d_psi);

@@ -35,7 +35,8 @@ class SharpError(RuntimeError):
 class SharpOptions(Structure):
     _fields_ = [("periodic", c_int), ("probe_every", c_int), ("probe_start", c_int), ("eps_D", c_float),
                 ("tile", c_int), ("merge_split", c_int), ("grad_groups", c_int), ("frame_launch", c_int),
-                ("fft_block", c_int), ("strip_rows", c_int), ("reserved", c_int * 2)]
+                ("fft_block", c_int), ("strip_rows", c_int), ("probe_center", c_int),
+                ("reserved", c_int * 1)]
 
 
 class SharpPlanInfo(Structure):
@@ -58,6 +59,7 @@ SIGNATURES = [
     ("sharp_set_data", c_int, [c_void_p, c_void_p]),
     ("sharp_set_probe", c_int, [c_void_p, c_void_p]),
     ("sharp_init_probe", c_int, [c_void_p]),
+    ("sharp_set_probe_constraint", c_int, [c_void_p, c_int, c_void_p]),
     ("sharp_set_object", c_int, [c_void_p, c_void_p]),
     ("sharp_raar_iterate", c_int, [c_void_p, c_int, c_float]),
     ("sharp_get_object", c_int, [c_void_p, c_void_p]),

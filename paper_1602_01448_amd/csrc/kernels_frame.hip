@@ -1104,6 +1104,90 @@ __global__ void __launch_bounds__(256) probe_finish_kernel(int MM, int chunks, c
     w_cur[p] = d > 0.f ? cscale(n, 1.0f / d) : make_float2(0.f, 0.f);
 }
 
+// Probe constraint in the Fourier domain (algorithm box, step 7): kind 1
+// multiplies by the mask, kind 2 keeps the phase and sets the magnitude
+// (sgn(0) := 1).
+__global__ void __launch_bounds__(256) probe_fourier_kernel(float2* __restrict__ W, const float* __restrict__ vals,
+                                                            int MM, int kind) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= MM) return;
+    const float2 v = W[p];
+    const float c = vals[p];
+    if (kind == 1) {
+        W[p] = cscale(v, c);
+    } else {
+        const float n2 = cabs2(v);
+        float2 s = make_float2(1.f, 0.f);
+        if (n2 > 0.f) s = cscale(v, rsqrtf(n2));
+        W[p] = cscale(s, c);
+    }
+}
+
+// Centre-of-mass correction (algorithm box, step 7): one workgroup forms the
+// centroid of |w|^2 (fixed-order FP32 sums), then rolls w circularly by
+// s = floor(m/2 - centroid + 1/2) per axis through tmp.
+__global__ void __launch_bounds__(1024) probe_center_kernel(float2* __restrict__ w, float2* __restrict__ tmp, int m) {
+    __shared__ float red[3][16];
+    __shared__ int shift[2];
+    const int MM = m * m, tid = threadIdx.x;
+    float t = 0.f, sy = 0.f, sx = 0.f;
+    for (int p = tid; p < MM; p += 1024) {
+        const float q = cabs2(w[p]);
+        t += q;
+        sy += (float)(p / m) * q;
+        sx += (float)(p % m) * q;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        t += __shfl_xor(t, o, 64);
+        sy += __shfl_xor(sy, o, 64);
+        sx += __shfl_xor(sx, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = t;
+        red[1][tid >> 6] = sy;
+        red[2][tid >> 6] = sx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float T = 0.f, Y = 0.f, X = 0.f;
+        for (int i = 0; i < 16; ++i) {
+            T += red[0][i];
+            Y += red[1][i];
+            X += red[2][i];
+        }
+        int a = 0, b = 0;
+        if (T > 0.f) {
+            const float half = (float)(m / 2);
+            a = (int)floorf(half - Y / T + 0.5f);
+            b = (int)floorf(half - X / T + 0.5f);
+        }
+        shift[0] = a;
+        shift[1] = b;
+    }
+    __syncthreads();
+    const int a = shift[0], b = shift[1];
+    if (a == 0 && b == 0) return;
+    for (int p = tid; p < MM; p += 1024) {
+        int y = (p / m + a) % m, x = (p % m + b) % m;
+        if (y < 0) y += m;
+        if (x < 0) x += m;
+        tmp[y * m + x] = w[p];
+    }
+    __syncthreads();
+    for (int p = tid; p < MM; p += 1024) w[p] = tmp[p];
+}
+
+hipError_t launch_probe_fourier(float2* W, const float* vals, int M, int kind, hipStream_t s) {
+    hipLaunchKernelGGL(probe_fourier_kernel, dim3((M * M + 255) / 256), dim3(256), 0, s, W, vals, M * M, kind);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_center(float2* w, float2* tmp, int M, hipStream_t s) {
+    hipLaunchKernelGGL(probe_center_kernel, dim3(1), dim3(1024), 0, s, w, tmp, M);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) gw_finish_kernel(int MM, int slots, const float2* __restrict__ part,
                                                         float2* __restrict__ gw) {
     const int p = blockIdx.x * 256 + threadIdx.x;

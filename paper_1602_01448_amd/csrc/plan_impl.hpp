@@ -22,7 +22,7 @@ inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
 
 struct Offsets {
     size_t tw, pos, tile_ptr, tile_frames, a, a_t, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
-    size_t w_cur, w_gat, tmp_w, tmp_w2, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sln, total;
+    size_t w_cur, w_gat, tmp_w, tmp_w2, pcons, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sln, total;
 };
 
 }  // namespace sharp
@@ -47,6 +47,7 @@ struct sharp_plan_s {
     float g = 1.f;
     long long iter = 0, hist_count = 0;
     bool gat_stale = false, last_probe_updated = false;
+    int pcons_kind = 0;         // probe constraint: 0 none, 1 Fourier mask, 2 Fourier amplitudes
     bool stage_gather = false;  // carry form: stage holds the next iteration's gathered, row-transformed frames
     // kernel timing (diagnostics): pending (start, stop) event pairs per category
     bool timing = false;

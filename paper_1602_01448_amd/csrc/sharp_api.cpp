@@ -194,6 +194,7 @@ static void layout(sharp_plan_s& p) {
     o.w_gat = take(MM * sizeof(float2));
     o.tmp_w = take(MM * sizeof(float2));
     o.tmp_w2 = take(MM * sizeof(float2));
+    o.pcons = take(MM * sizeof(float));
     o.mpart = take(p.split > 1 ? (size_t)p.ntiles * p.split * p.T * p.T * 2 * sizeof(float4) : 0);
     o.pnum = take((size_t)p.probe_chunks * MM * sizeof(float2));
     o.pden = take((size_t)p.probe_chunks * MM * sizeof(float));
@@ -227,7 +228,7 @@ extern "C" int sharp_plan_create(sharp_plan* out, int nx, int ny, int m, int K, 
             !(o.tile == 0 || o.tile == 16 || o.tile == 32 || o.tile == 64) || o.merge_split < 0 ||
             o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 2 ||
             !(o.fft_block == 0 || o.fft_block == 128 || o.fft_block == 256 || o.fft_block == 512) ||
-            o.strip_rows < 0 || o.strip_rows > 2)
+            o.strip_rows < 0 || o.strip_rows > 2 || o.probe_center < 0 || o.probe_center > 1)
             return SHARP_ERR_INVALID_ARG;
     }
     if (o.probe_start == 0) o.probe_start = 1;
@@ -282,6 +283,7 @@ extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
     p->ws_bytes = bytes;
     p->has_ws = true;
     p->has_data = p->has_probe = p->has_object = false;
+    p->pcons_kind = 0;
     std::vector<float2> tw(p->m);
     for (int t = 0; t < p->m; ++t) {
         const double ang = 2.0 * M_PI * t / p->m;
@@ -427,6 +429,14 @@ extern "C" int sharp_init_probe(sharp_plan p) {
     return SHARP_OK;
 }
 
+extern "C" int sharp_set_probe_constraint(sharp_plan p, int kind, const float* d_values) {
+    if (!p || kind < 0 || kind > 2 || (kind != 0 && !d_values)) return SHARP_ERR_INVALID_ARG;
+    if (!p->has_ws) return SHARP_ERR_NOT_READY;
+    if (kind) HIPCHK(launch_copy(p->ws + p->off.pcons, d_values, (size_t)p->m * p->m * sizeof(float), p->stream));
+    p->pcons_kind = kind;
+    return SHARP_OK;
+}
+
 extern "C" int sharp_set_object(sharp_plan p, const void* d_psi) {
     if (!p || !d_psi) return SHARP_ERR_INVALID_ARG;
     p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
@@ -463,6 +473,28 @@ static hipError_t space_to_carry(sharp_plan_s& p, const float2* src) {
     if (p.m == 128) return launch_fc128_convert(A, 0, p.stream);
     return launch_space_to_carry(A, p.stream);
 }
+// Algorithm box, step 7, after Eq. (standardprobe): the Fourier mask or
+// Fourier amplitude constraint, then the centre-of-mass correction.
+static hipError_t constrain_probe(sharp_plan_s& p) {
+    hipStream_t s = p.stream;
+    float2* w = p.at<float2>(p.off.w_cur);
+    float2* tmp = p.at<float2>(p.off.tmp_w);
+    if (p.pcons_kind) {
+        FrameArgs A = frame_args(p);
+        A.K = 1;
+        A.in = w;
+        A.out = tmp;
+        hipError_t e = launch_frame(FM_F, A, 0, s, nullptr);
+        if (e == hipSuccess) e = launch_probe_fourier(tmp, p.at<float>(p.off.pcons), p.m, p.pcons_kind, s);
+        A.in = tmp;
+        A.out = w;
+        if (e == hipSuccess) e = launch_frame(FM_FINV, A, 0, s, nullptr);
+        if (e != hipSuccess) return e;
+    }
+    if (p.opt.probe_center) return launch_probe_center(w, tmp, p.m, s);
+    return hipSuccess;
+}
+
 static int one_iteration(sharp_plan_s& p, float beta) {
     hipStream_t s = p.stream;
     const long long it = p.iter + 1;
@@ -527,6 +559,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
                                     beta, p.probe_chunks, p.at<float2>(p.off.pnum), p.at<float>(p.off.pden), s));
         HIPCHK(launch_probe_finish(p.m, p.probe_chunks, p.at<float2>(p.off.pnum), p.at<float>(p.off.pden),
                                    p.at<float2>(p.off.w_gat), p.at<float2>(p.off.w_cur), s));
+        HIPCHK(constrain_probe(p));
         int st = density(p);
         if (st) return st;
         if (t) t->end(TC_PROBE);

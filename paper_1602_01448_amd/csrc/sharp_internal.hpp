@@ -136,6 +136,9 @@ __host__ __device__ int fc128_groups(int K);
 hipError_t launch_fc128(const FrameArgs& A, hipStream_t s, const Timer* t, int* blocks_used);
 // to_space: A.out = F* A.in (A.in transposed carry); else A.out (transposed) = F A.in
 hipError_t launch_fc128_convert(const FrameArgs& A, int to_space, hipStream_t s);
+// probe constraints of the probe update: Fourier-domain mask / amplitudes, centre of mass
+hipError_t launch_probe_fourier(float2* W, const float* vals, int M, int kind, hipStream_t s);
+hipError_t launch_probe_center(float2* w, float2* tmp, int M, hipStream_t s);
 // amplitude-loss gradient at m = 128 (carry-form plans, which hold the transposed amplitudes)
 hipError_t launch_fc128_grad(const FrameArgs& A, int grid, hipStream_t s, const Timer* t, int* blocks_used);
 hipError_t batch_fc128_prepare(int* blocks_per_cu);

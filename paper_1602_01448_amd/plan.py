@@ -33,7 +33,7 @@ class Plan:
     def __init__(self, nx: int, ny: int, m: int, positions, periodic: bool = False, probe_every: int = 0,
                  probe_start: int = 1, eps_D: float = 0.0, tile: int = 0, merge_split: int = 0,
                  grad_groups: int = 0, frame_launch: int = 0, fft_block: int = 0, strip_rows: int = 0,
-                 device="cuda"):
+                 probe_center: bool = False, device="cuda"):
         pos = np.ascontiguousarray(np.asarray(positions), dtype=np.int32)
         if pos.ndim != 2 or pos.shape[1] != 2:
             raise ValueError("positions must be (K, 2) (y, x)")
@@ -42,7 +42,8 @@ class Plan:
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         opts = SharpOptions(int(periodic), int(probe_every), int(probe_start), float(eps_D), int(tile),
-                            int(merge_split), int(grad_groups), int(frame_launch), int(fft_block), int(strip_rows))
+                            int(merge_split), int(grad_groups), int(frame_launch), int(fft_block), int(strip_rows),
+                            int(bool(probe_center)))
         h = c_void_p()
         check(lib.sharp_plan_create(byref(h), self.nx, self.ny, self.m, self.K,
                                     pos.ctypes.data_as(POINTER(c_int32)), byref(opts)), "sharp_plan_create")
@@ -104,6 +105,19 @@ class Plan:
     def init_probe(self):
         self._stream()
         check(lib.sharp_init_probe(self._h), "sharp_init_probe")
+        return self
+
+    def set_probe_constraint(self, mask: torch.Tensor | None = None, amplitudes: torch.Tensor | None = None):
+        """Fourier mask m_w (takes precedence) or Fourier amplitudes a_w applied
+        after every probe update (algorithm box, step 7); neither = no constraint."""
+        vals = mask if mask is not None else amplitudes
+        kind = 1 if mask is not None else 2 if amplitudes is not None else 0
+        ptr = None
+        if vals is not None:
+            vals = _need(vals, torch.float32, (self.m, self.m), self.device, "mask" if kind == 1 else "amplitudes")
+            ptr = _ptr(vals)
+        self._stream()
+        check(lib.sharp_set_probe_constraint(self._h, kind, ptr), "sharp_set_probe_constraint")
         return self
 
     def set_object(self, psi: torch.Tensor):

@@ -41,7 +41,8 @@ def _create(L, n, m, pos, **kw):
     pos = np.ascontiguousarray(pos, dtype=np.int32)
     opts = SharpOptions(kw.get("periodic", 0), kw.get("probe_every", 0), kw.get("probe_start", 1),
                         kw.get("eps_D", 0.0), kw.get("tile", 0), kw.get("merge_split", 0), kw.get("grad_groups", 0),
-                        kw.get("frame_launch", 0), kw.get("fft_block", 0), kw.get("strip_rows", 0))
+                        kw.get("frame_launch", 0), kw.get("fft_block", 0), kw.get("strip_rows", 0),
+                        kw.get("probe_center", 0))
     if "reserved" in kw:
         opts.reserved[0] = kw["reserved"]
     st = L.sharp_plan_create(ctypes.byref(h), n, n, m, len(pos), pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -76,6 +77,7 @@ def test_validation(L):
     assert _create(L, 64, 32, [(0, 0)], frame_launch=3)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], fft_block=64)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], strip_rows=3)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], probe_center=2)[0] == -1
     assert _create(L, 300, 256, [(0, 0)], fft_block=512)[0] == 0
     h = ctypes.c_void_p()
     assert L.sharp_plan_create(ctypes.byref(h), 64, 64, 32, 0, None, None) == -1
@@ -115,6 +117,9 @@ def test_calls_before_workspace_are_not_ready(L):
     st, h = _create(L, 64, 32, [(0, 0), (8, 8)])
     assert st == 0
     assert L.sharp_set_data(h, ctypes.c_void_p(16)) == -4
+    assert L.sharp_set_probe_constraint(h, 1, ctypes.c_void_p(16)) == -4
+    assert L.sharp_set_probe_constraint(h, 3, ctypes.c_void_p(16)) == -1
+    assert L.sharp_set_probe_constraint(h, 2, None) == -1
     assert L.sharp_raar_iterate(h, 1, ctypes.c_float(1.5)) == -1          # beta outside (0, 1]
     assert L.sharp_raar_iterate(h, 1, ctypes.c_float(0.0)) == -1
     assert L.sharp_raar_iterate(h, 1, ctypes.c_float(0.75)) == -4
