@@ -131,6 +131,45 @@ def test_large_frames_one_iteration_sampled():
         assert rel(pv_gpu[ys, xs], ref) < 1e-5, (y0, x0)
 
 
+def test_fig3_shape_one_iteration_sampled():
+    """The paper's benchmark shape at full size (1000^2 periodic, 10,000 frames
+    of 128^2), in the launch configuration the benchmark times (m = 128
+    register-resident carry form): after one iteration, the frame-space carry
+    u' of sampled frames and psi_v on sampled windows (including windows across
+    the periodic seam) match the oracle computed frame by frame."""
+    from paper_1602_01448_amd import Plan
+    s = gen.fig3_scan()
+    I = O.forward_intensity(s.obj, s.probe, s.positions, periodic=True).astype(np.float32)
+    w, psi0, pos, n, m = c64(s.probe), c64(s.psi0), s.positions, s.n, s.m
+    p = Plan.tuned(n, n, m, pos, periodic=True)
+    assert p.info()["frame_launch"] == 2
+    p.set_data(to_dev(I)).set_probe(to_dev(w)).set_object(to_dev(psi0)).raar(1, s.beta)
+    st = p.state_parts(p.state())
+    u_gpu, pv_gpu = to_host(st["u"]), to_host(st["psi_v"])
+    beta = s.beta
+
+    def frame_terms(idx):
+        a = np.sqrt(I[idx].astype(np.float64))
+        z = O.Q(psi0, w, pos[idx], periodic=True)
+        y = O.P_a(z, a)
+        return beta * z + (1 - 2 * beta) * y, 2 * y - z
+
+    sample = np.array([0, 1, 99, 100, 5050, 9999])
+    u_ref, _ = frame_terms(sample)
+    assert rel(u_gpu[sample], u_ref) < 1e-5
+    Dp = O.dplus(O.illumination_density(w, pos, (n, n), periodic=True))
+    W = 32
+    for (y0, x0) in [(0, 0), (500, 500), (984, 984), (990, 10), (300, 968)]:
+        dy, dx = (y0 - pos[:, 0]) % n, (x0 - pos[:, 1]) % n
+        hit = np.where(((dy < m) | (dy > n - W)) & ((dx < m) | (dx > n - W)))[0]
+        _, v = frame_terms(hit)
+        acc = O.Qstar(v, w, pos[hit], (n, n), periodic=True)
+        ys = np.arange(y0, y0 + W) % n
+        xs = np.arange(x0, x0 + W) % n
+        ref = (Dp * acc)[np.ix_(ys, xs)]
+        assert rel(pv_gpu[np.ix_(ys, xs)], ref) < 1e-5, (y0, x0)
+
+
 def test_deterministic_bitwise():
     s = gen.config_scan(2)
     I, _ = _data(s)
