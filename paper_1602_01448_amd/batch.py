@@ -24,6 +24,7 @@ class Batch:
         h = c_void_p()
         check(lib.sharp_batch_create(byref(h), len(self.plans), arr), "sharp_batch_create")
         self._h = h
+        self._destroy = lib.sharp_batch_destroy   # bound now: usable while the interpreter shuts down
         nbytes = max(int(lib.sharp_batch_workspace_bytes(h)), 256)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream()
@@ -50,5 +51,5 @@ class Batch:
                 torch.cuda.synchronize(self.device)
             except Exception:
                 pass
-            lib.sharp_batch_destroy(h)
+            self._destroy(h)
             self._h = c_void_p()

@@ -530,6 +530,17 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
 #pragma unroll
             for (int q = 0; q < 8; ++q) ld2(A.in + fb, cb + 16 * q, v[2 * q], v[2 * q + 1]);
         } else {
+            // amplitudes and the first half of the carry are fetched ahead of the
+            // column transform (what the register budget allows)
+            float2 av8[8], u8[8];
+            if constexpr (MODE == FC_RAAR || MODE == FC_GRAD) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) av8[q] = ldf2(A.at + fb, cb + 16 * q);
+            }
+            if constexpr (MODE == FC_RAAR) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ld2(A.u + fb, cb + 16 * q, u8[2 * q], u8[2 * q + 1]);
+            }
 #pragma unroll
             for (int r = 0; r < 16; ++r) v[r] = lds[sw128(t + 8 * r, c)];
             l128_planB<1, true>(v, lds, twl, c, t);
@@ -541,7 +552,7 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
             } else if constexpr (MODE == FC_GRAD) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const float2 av = ldf2(A.at + fb, cb + 16 * q);
+                    const float2 av = av8[q];
                     v[2 * q] = cscale(op.modulus(cscale(v[2 * q], inv_m), av.x, true), 2.f);
                     v[2 * q + 1] = cscale(op.modulus(cscale(v[2 * q + 1], inv_m), av.y, true), 2.f);
                 }
@@ -550,8 +561,13 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     float2 u0, u1;
-                    ld2(A.u + fb, cb + 16 * q, u0, u1);
-                    const float2 av = ldf2(A.at + fb, cb + 16 * q);
+                    if (q < 4) {
+                        u0 = u8[2 * q];
+                        u1 = u8[2 * q + 1];
+                    } else {
+                        ld2(A.u + fb, cb + 16 * q, u0, u1);
+                    }
+                    const float2 av = av8[q];
                     const float2 z0 = cadd(u0, cscale(v[2 * q], inv_m)), z1 = cadd(u1, cscale(v[2 * q + 1], inv_m));
                     const float2 y0 = op.modulus(z0, av.x, true), y1 = op.modulus(z1, av.y, true);
                     st2(A.u + fb, cb + 16 * q, cadd(cscale(z0, b), cscale(y0, c1)), cadd(cscale(z1, b), cscale(y1, c1)));

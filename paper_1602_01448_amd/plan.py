@@ -48,6 +48,7 @@ class Plan:
         check(lib.sharp_plan_create(byref(h), self.nx, self.ny, self.m, self.K,
                                     pos.ctypes.data_as(POINTER(c_int32)), byref(opts)), "sharp_plan_create")
         self._h = h
+        self._destroy = lib.sharp_plan_destroy   # bound now: usable while the interpreter shuts down
         self.positions = pos
         nbytes = lib.sharp_workspace_bytes(h)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -79,7 +80,7 @@ class Plan:
                 torch.cuda.synchronize(self.device)
             except Exception:
                 pass
-            lib.sharp_plan_destroy(h)
+            self._destroy(h)
             self._h = c_void_p()
 
     def info(self) -> dict:
