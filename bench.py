@@ -111,7 +111,7 @@ def grad_form(reps: int = 10) -> dict:
     dev = torch.device("cuda", 0)
     s = gen.config_scan(4)
     psi, w = gen.gradient_point(s)
-    plan = Plan(s.n, s.n, s.m, s.positions, device=dev)
+    plan = Plan.tuned(s.n, s.n, s.m, s.positions, kind="grad", device=dev)
     I = plan.simulate(torch.from_numpy(s.obj.astype(np.complex64)).to(dev),
                       torch.from_numpy(s.probe.astype(np.complex64)).to(dev))
     plan.set_data(I)

@@ -3,11 +3,13 @@
 Times candidate launch configurations of the library on the GPU and keeps the
 fastest per geometry:
 
-* merge tile side (16, 32, 64) and frame-chunk split of the overlap merge;
-* for 256 x 256 frames, the form of the iteration (Fourier-domain carry with
-  the merge fused into the last pass, or frame-space carry with a separate
-  merge) and, for the latter, the pass workgroup size (128, 256 or 512
+* the form of the iteration for 128 x 128 and 256 x 256 frames (carry in
+  the Fourier domain or in frame space), for the 256 x 256 Fourier-carry
+  form the strip height of the fused merge (1 or 2 object rows), and for the
+  256 x 256 frame-space form the pass workgroup size (128, 256 or 512
   threads, i.e. 8, 16 or 32 rows / columns of a frame per workgroup);
+* merge tile side (16, 32, 64) and frame-chunk split of the overlap merge,
+  for every form that uses the tile merge;
 * the workgroup count of the gradient frame kernel.
 
 Candidates are timed with HIP events over a few RAAR iterations (or gradient
@@ -79,9 +81,18 @@ def _merge_candidates(n: int):
 
 
 def _frame_candidates(m: int):
-    if m != 256:
-        return [{}]
-    return [{"frame_launch": 2}] + [{"frame_launch": 1, "fft_block": b} for b in (128, 256, 512)]
+    if m == 256:
+        return ([{"frame_launch": 2, "strip_rows": r} for r in (1, 2)]
+                + [{"frame_launch": 1, "fft_block": b} for b in (128, 256, 512)])
+    if m == 128:
+        return [{"frame_launch": 2}, {"frame_launch": 1}]
+    return [{}]
+
+
+def _uses_tile_merge(m: int, frame_opts: dict) -> bool:
+    """Every form except the 256 x 256 Fourier-carry form (whose merge is
+    fused into its strip pass) ends with the tile merge."""
+    return not (m == 256 and frame_opts.get("frame_launch") == 2)
 
 
 def _synthetic(plan: Plan, seed: int):
@@ -132,30 +143,24 @@ def _time_grad(plan: Plan, reps: int) -> float:
 
 def tune_raar(nx: int, ny: int, m: int, positions, periodic: bool = False, iters: int = 3, reps: int = 3,
               path: str = CACHE, verbose: bool = False) -> dict:
-    """Fastest (merge, frame-phase) options for RAAR on this geometry; cached."""
+    """Fastest launch options for RAAR on this geometry: every form of the
+    iteration, and for the forms that end with the tile merge every merge
+    candidate; cached."""
     key = geometry_key("raar", nx, ny, m, positions, periodic)
     results = []
-    best_merge, best_t = {}, float("inf")
-    for mc in _merge_candidates(max(nx, ny)):        # merge options with the default frame phase
-        p = Plan(nx, ny, m, positions, periodic=periodic, **mc)
-        t = _time_raar(p, iters, reps)
-        results.append((mc, t))
-        if verbose:
-            print(f"  {mc}: {t:.4f} ms/iteration", flush=True)
-        if t < best_t:
-            best_merge, best_t = mc, t
-        del p
-    best = dict(best_merge)
-    for fc in [c for c in _frame_candidates(m) if c and c.get("frame_launch") != 2]:
-        opts = {**best_merge, **fc}
-        p = Plan(nx, ny, m, positions, periodic=periodic, **opts)
-        t = _time_raar(p, iters, reps)
-        results.append((opts, t))
-        if verbose:
-            print(f"  {opts}: {t:.4f} ms/iteration", flush=True)
-        if t < best_t:
-            best, best_t = opts, t
-        del p
+    best, best_t = {}, float("inf")
+    for fc in _frame_candidates(m):
+        merges = _merge_candidates(max(nx, ny)) if _uses_tile_merge(m, fc) else [{}]
+        for mc in merges:
+            opts = {**fc, **mc}
+            p = Plan(nx, ny, m, positions, periodic=periodic, **opts)
+            t = _time_raar(p, iters, reps)
+            results.append((opts, t))
+            if verbose:
+                print(f"  {opts}: {t:.4f} ms/iteration", flush=True)
+            if t < best_t:
+                best, best_t = opts, t
+            del p
     cache = load_cache(path)
     cache[key] = {"options": best, "ms_per_iteration": round(best_t, 5), "tried": len(results),
                   "when": time.strftime("%Y-%m-%d %H:%M:%S")}
@@ -190,7 +195,7 @@ def main() -> None:
     from sharp_data import gen
 
     ap = argparse.ArgumentParser(description="tune launch shapes of the benchmark workloads")
-    ap.add_argument("--workloads", default="1,2,3,4,batch")
+    ap.add_argument("--workloads", default="1,2,3,4,fig3")
     ap.add_argument("--path", default=CACHE)
     args = ap.parse_args()
     for w in args.workloads.split(","):
@@ -198,6 +203,11 @@ def main() -> None:
             for s in gen.batch_scans():
                 print(f"tuning raar {s.name}", flush=True)
                 tune_raar(s.n, s.n, s.m, s.positions, path=args.path, reps=2, iters=2)
+            continue
+        if w == "fig3":
+            s = gen.fig3_scan()
+            print(f"tuning raar {s.name}", flush=True)
+            print(tune_raar(s.n, s.n, s.m, s.positions, periodic=True, path=args.path, verbose=True), flush=True)
             continue
         s = gen.config_scan(int(w))
         if int(w) == 4:

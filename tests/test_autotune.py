@@ -13,7 +13,11 @@ def test_candidates_and_keys(tmp_path):
     assert all(x["merge_split"] >= 1 for x in c)
     assert any(x["merge_split"] > 1 for x in at._merge_candidates(128))
     f = at._frame_candidates(256)
-    assert {"frame_launch": 2} in f and {"frame_launch": 1, "fft_block": 512} in f
+    assert {"frame_launch": 2, "strip_rows": 2} in f and {"frame_launch": 1, "fft_block": 512} in f
+    assert not at._uses_tile_merge(256, {"frame_launch": 2, "strip_rows": 1})
+    assert at._uses_tile_merge(256, {"frame_launch": 1, "fft_block": 256})
+    assert at._frame_candidates(128) == [{"frame_launch": 2}, {"frame_launch": 1}]
+    assert at._uses_tile_merge(128, {"frame_launch": 2})
     assert at._frame_candidates(64) == [{}]
     pos = gen.raster_positions(5, 10, 80, 32)
     k1 = at.geometry_key("raar", 80, 80, 32, pos, False)
