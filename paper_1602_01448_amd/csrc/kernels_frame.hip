@@ -474,6 +474,19 @@ enum Fc128Mode : int { FC_RAAR = 0, FC_TO_SPACE = 1, FC_TO_CARRY = 2, FC_GRAD = 
 template <int MODE>
 using Fc128Op = ModOp<MODE == FC_GRAD ? FM_GRAD : FM_RAAR, 128>;
 
+constexpr size_t kFc128Smem = (size_t)(128 * 128 + 128) * sizeof(float2);
+constexpr int kFc128Groups = 256;
+
+// Workgroup b takes frames s, s + G, s + 2G, ... with s = fc128_slot(b, G)
+// and writes one residual partial; the batched form runs the same (scan, b)
+// items, so both sum the residual in the same order.  Workgroups are spread
+// over the XCDs round-robin (b mod 8), so the slot map gives each XCD a run of
+// G/8 consecutive frames at a time: neighbouring frames gather overlapping
+// object windows, which then hit that XCD's L2.
+__host__ __device__ int fc128_groups(int K) { return K < 1 ? 1 : (K < kFc128Groups ? K : kFc128Groups); }
+__host__ __device__ int fc128_slot(int b, int G) { return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3); }
+
+
 // One frame f.  RAAR: the carry-form step (reads A.u = U transposed, A.at =
 // amplitudes transposed, gathers psi; writes U' and v = conj(w) y).
 // FC_TO_SPACE: A.in (U transposed) -> A.out = F* U (natural layout).
@@ -611,7 +624,7 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
                 st2(A.v + fb, o, cconjmul(w0, r0), cconjmul(w1, r1));
                 float2* gp = A.gw_part + (size_t)blockIdx.x * MM;
                 float2 g0 = make_float2(0.f, 0.f), g1 = g0;
-                if (f != (int)blockIdx.x) ld2(gp, o, g0, g1);   // not this workgroup's first frame
+                if (f != fc128_slot(blockIdx.x, gridDim.x)) ld2(gp, o, g0, g1);   // not the workgroup's first frame
                 st2(gp, o, cadd(g0, cconjmul(ldc(A.psi, orow + gx0), r0)), cadd(g1, cconjmul(ldc(A.psi, orow + gx1), r1)));
             } else {
                 st2(A.out + fb, o, cscale(v[2 * q], inv_m), cscale(v[2 * q + 1], inv_m));
@@ -629,7 +642,8 @@ __global__ void __launch_bounds__(1024) fc128_kernel(FrameArgs A) {
     for (int t = threadIdx.x; t < 128; t += 1024) twl[t] = A.tw[t];
     __syncthreads();
     Fc128Op<MODE> op{nullptr, nullptr, 0.f};
-    for (int f = blockIdx.x; f < A.K; f += gridDim.x) {
+    const int first = fc128_slot(blockIdx.x, gridDim.x);
+    for (int f = first; f < A.K; f += gridDim.x) {
         fc128_frame<MODE>(A, f, lds, twl, op);
         if constexpr (MODE == FC_TO_SPACE || MODE == FC_TO_CARRY)
             __syncthreads();   // conversions start or end on the column side
@@ -639,14 +653,6 @@ __global__ void __launch_bounds__(1024) fc128_kernel(FrameArgs A) {
         if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
     }
 }
-
-constexpr size_t kFc128Smem = (size_t)(128 * 128 + 128) * sizeof(float2);
-constexpr int kFc128Groups = 256;
-
-// Workgroup b takes frames b, b + G, b + 2G, ... and writes one residual
-// partial; the batched form runs the same (scan, b) items, so both sum the
-// residual in the same order.
-__host__ __device__ int fc128_groups(int K) { return K < 1 ? 1 : (K < kFc128Groups ? K : kFc128Groups); }
 
 template <int MODE>
 static hipError_t launch_fc128_mode(const FrameArgs& A, hipStream_t s) {
@@ -706,7 +712,7 @@ __global__ void __launch_bounds__(1024) batch_fc128_kernel(const FrameArgs* __re
         const FrameArgs A = D[w.x];
         const int G = fc128_groups(A.K);
         Fc128Op<FC_RAAR> op{nullptr, nullptr, 0.f};
-        for (int f = w.y; f < A.K; f += G) fc128_frame<FC_RAAR>(A, f, lds, twl, op);
+        for (int f = fc128_slot(w.y, G); f < A.K; f += G) fc128_frame<FC_RAAR>(A, f, lds, twl, op);
         const float s = block_sum(op.resid, red);
         if (threadIdx.x == 0) A.resid[w.y] = s;
     }
