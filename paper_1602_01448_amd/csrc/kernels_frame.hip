@@ -114,8 +114,8 @@ __device__ __forceinline__ float2 ldc(const float2* __restrict__ p, unsigned i) 
     return *reinterpret_cast<const float2*>(byte_at(p, i, 8u));
 }
 
-// g * w * psi for the gather of the m = 256 carry form (row pass and strip
-// pass), evaluated without contraction.
+// g * w * psi for the gather of the m = 128 kernel, evaluated without
+// contraction.
 __device__ __forceinline__ float2 gather_z(float2 w, float2 p, float g) {
 #pragma clang fp contract(off)
     return make_float2((w.x * p.x - w.y * p.y) * g, (w.x * p.y + w.y * p.x) * g);
@@ -157,8 +157,8 @@ __device__ __forceinline__ void prologue2(const FrameArgs& A, int frame, int y, 
         float2 p0, p1, w0, w1;
         gather2(A, frame, y, x, p0, p1);
         ld2(A.w_g, pix, w0, w1);
-        z0 = gather_z(w0, p0, A.g);
-        z1 = gather_z(w1, p1, A.g);
+        z0 = cmul(w0, p0);   // g is applied by the column pass
+        z1 = cmul(w1, p1);
     } else {  // GRAD, SIM, Q
         float2 w0, w1;
         gather2(A, frame, y, x, t0, t1);
@@ -1383,16 +1383,17 @@ __device__ float col_carry_item(const FrameArgs& A, int it, float2* lds, const f
     __syncthreads();
     NoPost none;
     fft_1d<M, 1, NT, CB, ColLayCB<CB>>(lds, twl, none);
-    // pointwise in the Fourier domain
-    const float inv_m = 1.0f / M, b = A.beta, c1 = 1.f - 2.f * A.beta;
+    // pointwise in the Fourier domain; the stage holds the transform of the
+    // unscaled gather w_g T psi_v, so the coefficient g joins the 1/m of F
+    const float gm = A.g * (1.0f / M), b = A.beta, c1 = 1.f - 2.f * A.beta;
     ModOp<FM_RAAR, M> op{nullptr, nullptr, 0.f};
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int e0 = 2 * (tid + NT * k);
         const float2 u0 = uc[2 * k], u1 = uc[2 * k + 1];
         const float2 av = ac[k];
-        const float2 z0 = cadd(u0, cscale(lds[pidx(e0)], inv_m));
-        const float2 z1 = cadd(u1, cscale(lds[pidx(e0 + 1)], inv_m));
+        const float2 z0 = cadd(u0, cscale(lds[pidx(e0)], gm));
+        const float2 z1 = cadd(u1, cscale(lds[pidx(e0 + 1)], gm));
         const float2 y0 = op.modulus(z0, av.x, true), y1 = op.modulus(z1, av.y, true);
         st2(A.u + blk, e0, cadd(cscale(z0, b), cscale(y0, c1)), cadd(cscale(z1, b), cscale(y1, c1)));
         lds[pidx(e0)] = csub(cscale(y0, 2.f), z0);
@@ -1426,7 +1427,7 @@ __global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
 
 // Inverse row FFTs of the frame rows that land in object strip s (SH rows),
 // multiplied by conj(w) and summed in ascending frame order into the strip,
-// then psi_v = D^+ * sum.  Thread t owns the strip pixels whose column is
+// then psi_v = D^+ * sum (the 1/m of F* is applied to the sum).  Thread t owns the strip pixels whose column is
 // congruent to t modulo 256, so the per-pixel order of the sum is the frame
 // order and no two threads touch one pixel.
 //
@@ -1438,14 +1439,16 @@ __global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
 // thread and held in registers for the whole strip.  Butterflies, twiddles
 // and their order are those of the LDS transforms of the row passes; results
 // agree with them to rounding (the compiler may fuse multiplies and adds
-// differently in the two code shapes).
+// differently in the two code shapes).  The transform threads also multiply
+// their elements by conj(w) of the line's frame row (read contiguously), so
+// the sum only adds.
 //
 // Lane l of every wave also holds the record (frame, frame row, frame x) of
 // line l of a batch for the column-owned sum.  When every frame's columns map
 // onto residues without wrap trouble (no periodic wrap, or nx a multiple of
 // 256) thread t reads, for each line, the one frame column x with px + x = t
 // (mod 256); otherwise (periodic wrap with nx not a multiple of 256) a thread
-// walks its own columns and reads w per use.
+// walks its own columns.
 
 constexpr int kStripLines = 16;
 
@@ -1487,8 +1490,8 @@ __device__ __forceinline__ void line_stage2(float2 (&v)[16], const float2* lds, 
 }
 
 // The next iteration's frames are z = beta w T psi_v + u (carry form, Fourier
-// side), and the row pass of that iteration only gathers beta w T psi_v and
-// row-transforms it.  Frame row r of frame f reads object row py + r only, so
+// side), and the row pass of that iteration only gathers w T psi_v and
+// row-transforms it (the column pass applies beta).  Frame row r of frame f reads object row py + r only, so
 // the strip that has just finished psi_v on its rows forms those gathered,
 // row-transformed lines itself (the row pass's transform, equal to rounding)
 // and writes them where the row pass would: the next iteration starts at the
@@ -1500,7 +1503,6 @@ __device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b,
     const int tid = opaque_tid(), line = tid >> 4, j = tid & 15;
     const int SH = S.SH, FPB = LINES / SH, nx = A.nx;
     const int sr = SH == 2 ? (line & 1) : 0;
-    const float g = A.beta;
     float2 ww[16];
     // an absent line (record frame -1) has row 0 and x 0: its values stay in
     // bounds and are never stored
@@ -1512,11 +1514,18 @@ __device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b,
     loadw(cur);
     for (int i = b; i < e; i += FPB) {
         float2 v[16];
+        const float2* prow = psi_rows + sr * nx;
+        if (!A.periodic) {
+            const float2* p = prow + cur.z + j;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            int gx = cur.z + j + 16 * r;
-            if (gx >= nx) gx -= nx;
-            v[r] = gather_z(ww[r], psi_rows[sr * nx + gx], g);
+            for (int r = 0; r < 16; ++r) v[r] = cmul(ww[r], p[16 * r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int gx = cur.z + j + 16 * r;
+                if (gx >= nx) gx -= nx;
+                v[r] = cmul(ww[r], prow[gx]);
+            }
         }
         line_stage1<1>(v, lds, line, j);
         const int4 nxt = strip_my_record(S, i + FPB, e, line);
@@ -1563,13 +1572,11 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
         const int4 mine_next = strip_my_record(S, i + FPB, e, line);
         const int4 next = strip_records(S, i + FPB, e, lane);
         if (i + FPB < e) load_line(mine_next);   // next batch in flight during this one
-        float2 wv[LINES];
-        if (owned) {
+        float2 ww[16];                           // conj(w) is applied to the line here
+        {
+            const float2* wrow = A.w + (unsigned)mine.y * M + j;
 #pragma unroll
-            for (int l = 0; l < LINES; ++l) {
-                const unsigned x = (unsigned)(tid - __builtin_amdgcn_readlane(cur.z, l)) & (M - 1);
-                wv[l] = ldc(A.w, (unsigned)__builtin_amdgcn_readlane(cur.y, l) * M + x);
-            }
+            for (int q = 0; q < 16; ++q) ww[q] = wrow[16 * q];
         }
         line_sync();
         {
@@ -1577,7 +1584,7 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
             float2 t[16];
             line_stage2<-1>(t, lds, line, j, tw);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) lds[pidx(line * M + j + 16 * q)] = t[q];
+            for (int q = 0; q < 16; ++q) lds[pidx(line * M + j + 16 * q)] = cconjmul(ww[q], t[q]);
         }
         __syncthreads();
         if (owned) {
@@ -1588,23 +1595,20 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
                 const int x = (tid - px) & (M - 1);
                 int gx = px + x;
                 if (gx >= nx) gx -= nx;
-                const float2 yv = cscale(lds[pidx(l * M + x)], inv_m);
                 float2& a = acc[(SH == 2 ? (l & 1) : 0) * nx + gx];
-                a = cadd(a, cconjmul(wv[l], yv));
+                a = cadd(a, lds[pidx(l * M + x)]);
             }
         } else {
             for (int l = 0; l < LINES; ++l) {
                 if (__builtin_amdgcn_readlane(cur.x, l) < 0) continue;
-                const int r = __builtin_amdgcn_readlane(cur.y, l), px = __builtin_amdgcn_readlane(cur.z, l);
+                const int px = __builtin_amdgcn_readlane(cur.z, l);
                 const int sr = SH == 2 ? (l & 1) : 0;
                 for (int gx = tid; gx < nx; gx += NT) {
                     int x = gx - px;
                     if (x < 0) x += nx;
                     if ((unsigned)x >= (unsigned)M) continue;
-                    const float2 yv = cscale(lds[pidx(l * M + x)], inv_m);
-                    const float2 wq = ldc(A.w, (unsigned)(r * M + x));
                     float2& a = acc[sr * nx + gx];
-                    a = cadd(a, cconjmul(wq, yv));
+                    a = cadd(a, lds[pidx(l * M + x)]);
                 }
             }
         }
@@ -1617,7 +1621,7 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
         if (y >= ny) break;
         for (int gx = tid; gx < nx; gx += NT) {
             const unsigned o = (unsigned)y * (unsigned)nx + gx;
-            const float2 pv = cscale(acc[sr * nx + gx], S.Dinv[o]);
+            const float2 pv = cscale(acc[sr * nx + gx], S.Dinv[o] * inv_m);   // 1/m of F* applied once
             S.out[o] = pv;
             acc[sr * nx + gx] = pv;
         }
