@@ -212,15 +212,18 @@ def batched_form(iters: int = 20) -> dict:
             "speedup": round(ms_p / ms_b, 3)}
 
 
-# HBM bytes per launch of the large-frame kernels from rocprofv3 counters
+# HBM bytes per iteration of the large-frame kernels from rocprofv3 counters
 # (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the ratios the same counters give
-# for a 1 GiB device copy), taken on the kernels as they stand; the summary
-# with its commands is profiles/raar_carry_form_2048obj_2025x256_kernels.txt.
-MEASURED_TRAFFIC = {("cols", 2): 4_778_900_000, ("merge", 2): 2_219_100_000}
+# for a 1 GiB device copy), summed over the kernel's launches in one
+# iteration, taken on the kernels as they stand; the summary with its
+# commands is profiles/raar_carry_form_2048obj_2025x256_kernels.txt.  To be
+# emptied whenever these kernels change until the counters are taken again.
+MEASURED_TRAFFIC = {("cols", 2): 4_778_900_000, ("merge", 2): 2_216_600_000}
 
 
-def traffic_for(kernel: str, form: int):
-    return MEASURED_TRAFFIC.get((kernel, form))
+def traffic_for(kernel: str, form: int, launches_per_iteration: float):
+    v = MEASURED_TRAFFIC.get((kernel, form))
+    return None if v is None else round(v / launches_per_iteration)
 
 
 def copy_calibration(nbytes: int = 1 << 30) -> None:
@@ -363,10 +366,13 @@ def main() -> int:
         out["kernels"] = per
         # dominant kernel: the longest mean launch among those with algorithmic bytes
         dom = max((k for k in per if k in B), key=lambda k: per[k]["ms_mean"])
-        ach = B[dom] / (per[dom]["ms_mean"] / 1e3) / 1e9
+        # bytes per launch (a kernel may be launched more than once per step)
+        lpi = per[dom]["launches"] / args.steps
+        per_launch = B[dom] / lpi
+        ach = per_launch / (per[dom]["ms_mean"] / 1e3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom, form),
-                           "kernel": kernel_names(s.m, form).get(dom, dom), "alg_bytes_per_launch": B[dom],
+                           "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom, form, lpi),
+                           "kernel": kernel_names(s.m, form).get(dom, dom), "alg_bytes_per_launch": round(per_launch),
                            "launch_ms": per[dom]["ms_mean"]}
     del plan
     if not args.no_forms:

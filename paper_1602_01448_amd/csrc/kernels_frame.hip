@@ -1637,7 +1637,7 @@ __global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripA
     float2* acc = twl + 256;
     for (int t = threadIdx.x; t < 256; t += 256) twl[t] = A.tw[t];
     __syncthreads();
-    strip_merge_item(A, S, blockIdx.x, lds, twl, acc);
+    strip_merge_item(A, S, S.strip0 + blockIdx.x, lds, twl, acc);
 }
 
 // Batched form: phase 0 gather + row FFTs, 1 column pass with the carry,
@@ -1769,33 +1769,41 @@ size_t strip_smem_bytes(int SH, int nx) {
     return (size_t)(pidx(16 * 256) + 256 + SH * nx) * sizeof(float2);
 }
 
-hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int4* strip_lines, int SH,
-                                 int nstrips, const float* Dinv, float2* psi_out, bool gather, bool next_gather,
-                                 hipStream_t s, const Timer* tp, int* blocks_used) {
+hipError_t launch_row_gather_256(const FrameArgs& A, hipStream_t s, const Timer* tp) {
     const Timer& t = tp ? *tp : kNoTimer;
     using C = MP<256, 256>;
-    const int rows = A.K * C::NRB, cols = A.K * C::NCB;
-    if (gather) {
-        t.begin(TC_FRAME);
-        hipLaunchKernelGGL((mp_row_fwd<256, FM_GATHER, 256>), dim3(rows), dim3(256), C::SMEM, s, A);
-        t.end(TC_FRAME);
-    }
-    t.begin(TC_COLS);
-    hipLaunchKernelGGL(col_carry_kernel, dim3(cols), dim3(256), C::SMEM, s, A);
-    t.end(TC_COLS);
-    *blocks_used = cols;
+    t.begin(TC_FRAME, s);
+    hipLaunchKernelGGL((mp_row_fwd<256, FM_GATHER, 256>), dim3(A.K * C::NRB), dim3(256), C::SMEM, s, A);
+    t.end(TC_FRAME, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_carry_256(const FrameArgs& A, hipStream_t s, const Timer* tp) {
+    const Timer& t = tp ? *tp : kNoTimer;
+    using C = MP<256, 256>;
+    if (A.K <= 0) return hipSuccess;
+    t.begin(TC_COLS, s);
+    hipLaunchKernelGGL(col_carry_kernel, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A);
+    t.end(TC_COLS, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_strip_256(const FrameArgs& A, const StripArgs& S, int s0, int s1, hipStream_t s,
+                            const Timer* tp) {
+    const Timer& t = tp ? *tp : kNoTimer;
+    if (s1 <= s0) return hipSuccess;
     static bool attr = false;
-    const size_t smem = strip_smem_bytes(SH, A.nx);
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)strip_merge_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    StripArgs S{strip_ptr, strip_lines, Dinv, psi_out, SH, next_gather ? 1 : 0};
-    t.begin(TC_MERGE);
-    hipLaunchKernelGGL(strip_merge_kernel, dim3(nstrips), dim3(256), smem, s, A, S);
-    t.end(TC_MERGE);
+    StripArgs S2 = S;
+    S2.strip0 = s0;
+    t.begin(TC_MERGE, s);
+    hipLaunchKernelGGL(strip_merge_kernel, dim3(s1 - s0), dim3(256), strip_smem_bytes(S.SH, A.nx), s, A, S2);
+    t.end(TC_MERGE, s);
     return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ struct sharp_plan_s {
     bool gat_stale = false, last_probe_updated = false;
     int pcons_kind = 0;         // probe constraint: 0 none, 1 Fourier mask, 2 Fourier amplitudes
     bool stage_gather = false;  // carry form: stage holds the next iteration's gathered, row-transformed frames
+
     // kernel timing (diagnostics): pending (start, stop) event pairs per category
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;

@@ -17,7 +17,7 @@
 
 using namespace sharp;
 
-static void timer_mark(void* ctx, int cat, int begin) {
+static void timer_mark(void* ctx, int cat, int begin, hipStream_t s) {
     sharp_plan_s& p = *static_cast<sharp_plan_s*>(ctx);
     hipEvent_t e = nullptr;
     if (!p.ev_pool.empty()) {
@@ -26,7 +26,7 @@ static void timer_mark(void* ctx, int cat, int begin) {
     } else if (hipEventCreate(&e) != hipSuccess) {
         return;
     }
-    if (hipEventRecord(e, p.stream) != hipSuccess) {
+    if (hipEventRecord(e, s ? s : p.stream) != hipSuccess) {
         p.ev_pool.push_back(e);
         return;
     }
@@ -508,9 +508,12 @@ static int one_iteration(sharp_plan_s& p, float beta) {
         // frame phase and merge in one sequence; psi_v is final afterwards.  The
         // strip pass also prepares the next iteration's gather unless a probe
         // update (which reuses the stage buffer) follows.
-        HIPCHK(launch_carry_raar_256(A, p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.SH, p.nstrips,
-                                     p.at<float>(p.off.Dinv), p.at<float2>(p.off.psi_v), !p.stage_gather,
-                                     !probe_due, s, t, &blocks));
+        const StripArgs S{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
+                          p.at<float2>(p.off.psi_v), p.SH, probe_due ? 0 : 1, 0};
+        if (!p.stage_gather) HIPCHK(launch_row_gather_256(A, s, t));
+        HIPCHK(launch_col_carry_256(A, s, t));
+        HIPCHK(launch_strip_256(A, S, 0, p.nstrips, s, t));
+        blocks = p.K * 16;
         p.stage_gather = !probe_due;
     } else if (p.carry_form()) {
         HIPCHK(launch_fc128(A, s, t, &blocks));

@@ -176,7 +176,7 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         fa[s] = frame_args(p);
         ma[s] = merge_args(p);
         sa[s] = StripArgs{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
-                          p.at<float2>(p.off.psi_v), p.SH, 1};
+                          p.at<float2>(p.off.psi_v), p.SH, 1, 0};
         ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),
                         p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
     }

@@ -85,9 +85,9 @@ enum TimerCat : int { TC_FRAME = 0, TC_COLS = 1, TC_FRAME_OUT = 2, TC_MERGE = 3,
                       TC_COPY = 6, TC_N = 8 };
 struct Timer {
     void* ctx = nullptr;
-    void (*mark)(void* ctx, int cat, int begin) = nullptr;
-    void begin(int c) const { if (mark) mark(ctx, c, 1); }
-    void end(int c) const { if (mark) mark(ctx, c, 0); }
+    void (*mark)(void* ctx, int cat, int begin, hipStream_t s) = nullptr;  // s = nullptr: the plan's stream
+    void begin(int c, hipStream_t s = nullptr) const { if (mark) mark(ctx, c, 1, s); }
+    void end(int c, hipStream_t s = nullptr) const { if (mark) mark(ctx, c, 0, s); }
 };
 
 // launchers (kernels_frame.hip)
@@ -128,7 +128,8 @@ struct StripArgs {
     float2* __restrict__ out;        // psi_v
     int SH;                          // object rows per strip
     int next_gather;                 // also form the next iteration's gathered, row-transformed
-                                     // frame rows (w * T psi_v scaled by beta) in the stage buffer
+                                     // frame rows (w * T psi_v) in the stage buffer
+    int strip0;                      // first strip of the launch (workgroup b takes strip strip0 + b)
 };
 size_t carry_phase_smem();
 // m = 128 with the RAAR carry kept in the Fourier domain
@@ -147,9 +148,11 @@ hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu);
 hipError_t launch_batch_carry(int phase, const FrameArgs* D, const StripArgs* SD, const int2* items, int n, int grid,
                               size_t smem, hipStream_t s);
 size_t strip_smem_bytes(int SH, int nx);
-hipError_t launch_carry_raar_256(const FrameArgs& A, const int* strip_ptr, const int4* strip_lines, int SH,
-                                 int nstrips, const float* Dinv, float2* psi_out, bool gather, bool next_gather,
-                                 hipStream_t s, const Timer* t, int* blocks_used);
+// m = 256 Fourier-carry form: gather + row transforms (first iteration only),
+// column pass over the K frames of A, strip pass over strips [s0, s1)
+hipError_t launch_row_gather_256(const FrameArgs& A, hipStream_t s, const Timer* t);
+hipError_t launch_col_carry_256(const FrameArgs& A, hipStream_t s, const Timer* t);
+hipError_t launch_strip_256(const FrameArgs& A, const StripArgs& S, int s0, int s1, hipStream_t s, const Timer* t);
 hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s);
 hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s);
 
