@@ -43,7 +43,7 @@ class SharpPlanInfo(Structure):
     _fields_ = [("nx", c_int), ("ny", c_int), ("m", c_int), ("K", c_int), ("periodic", c_int),
                 ("tile", c_int), ("tiles_x", c_int), ("tiles_y", c_int), ("merge_split", c_int),
                 ("grad_groups", c_int), ("frame_launch", c_int), ("fft_block", c_int), ("strip_rows", c_int),
-                ("csr_nnz", c_longlong),
+                ("streaming", c_int), ("csr_nnz", c_longlong),
                 ("iteration", c_longlong)]
 
 

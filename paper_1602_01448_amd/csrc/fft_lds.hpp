@@ -33,6 +33,10 @@ __device__ __forceinline__ float2 cconjmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
 
+// clang vector types for the nontemporal load/store builtins
+typedef float sf4 __attribute__((ext_vector_type(4)));
+typedef float sf2 __attribute__((ext_vector_type(2)));
+
 // multiply by DIR * i
 template <int DIR>
 __device__ __forceinline__ float2 mul_i(float2 a) {

@@ -110,6 +110,40 @@ __device__ __forceinline__ float2 ldf2(const float* __restrict__ p, unsigned i) 
 __device__ __forceinline__ void stf2(float* __restrict__ p, unsigned i, float a, float b) {
     *reinterpret_cast<float2*>(const_cast<char*>(byte_at(p, i, 4u))) = make_float2(a, b);
 }
+// Streaming forms (nontemporal hint) for arrays that a pass reads or writes
+// once (the carry, the amplitudes, the stage buffer, the merge input): when
+// these arrays are larger than the last-level cache, the carry passes move
+// measurably more bytes per second with them.
+__device__ __forceinline__ void ld2s(const float2* __restrict__ p, unsigned i, float2& a, float2& b) {
+    const sf4 t = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(byte_at(p, i, 8u)));
+    a = make_float2(t.x, t.y);
+    b = make_float2(t.z, t.w);
+}
+__device__ __forceinline__ void st2s(float2* __restrict__ p, unsigned i, float2 a, float2 b) {
+    const sf4 t = {a.x, a.y, b.x, b.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<sf4*>(const_cast<char*>(byte_at(p, i, 8u))));
+}
+__device__ __forceinline__ float2 ldf2s(const float* __restrict__ p, unsigned i) {
+    const sf2 t = __builtin_nontemporal_load(reinterpret_cast<const sf2*>(byte_at(p, i, 4u)));
+    return make_float2(t.x, t.y);
+}
+// NT selects the streaming form (a plan streams when its frame arrays exceed
+// the last-level cache; below that, the cached form keeps them resident).
+template <bool NT>
+__device__ __forceinline__ void ld2t(const float2* __restrict__ p, unsigned i, float2& a, float2& b) {
+    if constexpr (NT) ld2s(p, i, a, b);
+    else ld2(p, i, a, b);
+}
+template <bool NT>
+__device__ __forceinline__ void st2t(float2* __restrict__ p, unsigned i, float2 a, float2 b) {
+    if constexpr (NT) st2s(p, i, a, b);
+    else st2(p, i, a, b);
+}
+template <bool NT>
+__device__ __forceinline__ float2 ldf2t(const float* __restrict__ p, unsigned i) {
+    if constexpr (NT) return ldf2s(p, i);
+    else return ldf2(p, i);
+}
 __device__ __forceinline__ float2 ldc(const float2* __restrict__ p, unsigned i) {
     return *reinterpret_cast<const float2*>(byte_at(p, i, 8u));
 }
@@ -496,7 +530,7 @@ __host__ __device__ int fc128_slot(int b, int G) { return (G & 7) ? b : (b & 7) 
 // A.gw_part; each thread updates the same 16 pixels every frame).  Ends with
 // the row threads done with their rows: the next frame's first LDS writes
 // are made by the same threads, so frames need no barrier between them.
-template <int MODE>
+template <int MODE, bool NT>
 __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* lds, const float2* twl,
                                             Fc128Op<MODE>& op) {
     constexpr int M = 128, MM = M * M;
@@ -548,11 +582,11 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
             float2 av8[8], u8[8];
             if constexpr (MODE == FC_RAAR || MODE == FC_GRAD) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) av8[q] = ldf2(A.at + fb, cb + 16 * q);
+                for (int q = 0; q < 8; ++q) av8[q] = ldf2t<NT>(A.at + fb, cb + 16 * q);
             }
             if constexpr (MODE == FC_RAAR) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) ld2(A.u + fb, cb + 16 * q, u8[2 * q], u8[2 * q + 1]);
+                for (int q = 0; q < 4; ++q) ld2t<NT>(A.u + fb, cb + 16 * q, u8[2 * q], u8[2 * q + 1]);
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) v[r] = lds[sw128(t + 8 * r, c)];
@@ -578,12 +612,12 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
                         u0 = u8[2 * q];
                         u1 = u8[2 * q + 1];
                     } else {
-                        ld2(A.u + fb, cb + 16 * q, u0, u1);
+                        ld2t<NT>(A.u + fb, cb + 16 * q, u0, u1);
                     }
                     const float2 av = av8[q];
                     const float2 z0 = cadd(u0, cscale(v[2 * q], inv_m)), z1 = cadd(u1, cscale(v[2 * q + 1], inv_m));
                     const float2 y0 = op.modulus(z0, av.x, true), y1 = op.modulus(z1, av.y, true);
-                    st2(A.u + fb, cb + 16 * q, cadd(cscale(z0, b), cscale(y0, c1)), cadd(cscale(z1, b), cscale(y1, c1)));
+                    st2t<NT>(A.u + fb, cb + 16 * q, cadd(cscale(z0, b), cscale(y0, c1)), cadd(cscale(z1, b), cscale(y1, c1)));
                     v[2 * q] = csub(cscale(y0, 2.f), z0);
                     v[2 * q + 1] = csub(cscale(y1, 2.f), z1);
                 }
@@ -607,7 +641,7 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
             if constexpr (MODE == FC_RAAR) {
                 float2 w0, w1;
                 ld2(A.w, o, w0, w1);
-                st2(A.v + fb, o, cconjmul(w0, cscale(v[2 * q], inv_m)), cconjmul(w1, cscale(v[2 * q + 1], inv_m)));
+                st2t<NT>(A.v + fb, o, cconjmul(w0, cscale(v[2 * q], inv_m)), cconjmul(w1, cscale(v[2 * q + 1], inv_m)));
             } else if constexpr (MODE == FC_GRAD) {
                 // T psi is gathered again (the object reads hit the caches)
                 const int py = A.pos[2 * f], px = A.pos[2 * f + 1];
@@ -621,7 +655,7 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
                 float2 w0, w1;
                 ld2(A.w, o, w0, w1);
                 const float2 r0 = cscale(v[2 * q], inv_m), r1 = cscale(v[2 * q + 1], inv_m);
-                st2(A.v + fb, o, cconjmul(w0, r0), cconjmul(w1, r1));
+                st2t<NT>(A.v + fb, o, cconjmul(w0, r0), cconjmul(w1, r1));
                 float2* gp = A.gw_part + (size_t)blockIdx.x * MM;
                 float2 g0 = make_float2(0.f, 0.f), g1 = g0;
                 if (f != fc128_slot(blockIdx.x, gridDim.x)) ld2(gp, o, g0, g1);   // not the workgroup's first frame
@@ -633,7 +667,7 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
     }
 }
 
-template <int MODE>
+template <int MODE, bool NT>
 __global__ void __launch_bounds__(1024) fc128_kernel(FrameArgs A) {
     extern __shared__ float2 smem[];
     __shared__ float red[16];
@@ -644,7 +678,7 @@ __global__ void __launch_bounds__(1024) fc128_kernel(FrameArgs A) {
     Fc128Op<MODE> op{nullptr, nullptr, 0.f};
     const int first = fc128_slot(blockIdx.x, gridDim.x);
     for (int f = first; f < A.K; f += gridDim.x) {
-        fc128_frame<MODE>(A, f, lds, twl, op);
+        fc128_frame<MODE, NT>(A, f, lds, twl, op);
         if constexpr (MODE == FC_TO_SPACE || MODE == FC_TO_CARRY)
             __syncthreads();   // conversions start or end on the column side
     }
@@ -654,17 +688,23 @@ __global__ void __launch_bounds__(1024) fc128_kernel(FrameArgs A) {
     }
 }
 
-template <int MODE>
-static hipError_t launch_fc128_mode(const FrameArgs& A, hipStream_t s) {
+template <int MODE, bool NT>
+static hipError_t launch_fc128_nt(const FrameArgs& A, int grid, hipStream_t s) {
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)fc128_kernel<MODE>,
+        hipError_t e = hipFuncSetAttribute((const void*)fc128_kernel<MODE, NT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFc128Smem);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(fc128_kernel<MODE>, dim3(fc128_groups(A.K)), dim3(1024), kFc128Smem, s, A);
+    hipLaunchKernelGGL((fc128_kernel<MODE, NT>), dim3(grid), dim3(1024), kFc128Smem, s, A);
     return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_fc128_mode(const FrameArgs& A, hipStream_t s) {
+    return A.stream ? launch_fc128_nt<MODE, true>(A, fc128_groups(A.K), s)
+                    : launch_fc128_nt<MODE, false>(A, fc128_groups(A.K), s);
 }
 
 hipError_t launch_fc128(const FrameArgs& A, hipStream_t s, const Timer* tp, int* blocks_used) {
@@ -677,24 +717,19 @@ hipError_t launch_fc128(const FrameArgs& A, hipStream_t s, const Timer* tp, int*
 }
 
 hipError_t launch_fc128_convert(const FrameArgs& A, int to_space, hipStream_t s) {
-    return to_space ? launch_fc128_mode<FC_TO_SPACE>(A, s) : launch_fc128_mode<FC_TO_CARRY>(A, s);
+    // the conversions use none of the streaming accesses
+    return to_space ? launch_fc128_nt<FC_TO_SPACE, false>(A, fc128_groups(A.K), s)
+                    : launch_fc128_nt<FC_TO_CARRY, false>(A, fc128_groups(A.K), s);
 }
 
 hipError_t launch_fc128_grad(const FrameArgs& A, int grid, hipStream_t s, const Timer* tp, int* blocks_used) {
     const Timer& t = tp ? *tp : kNoTimer;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)fc128_kernel<FC_GRAD>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFc128Smem);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
     grid = std::max(1, std::min(grid, A.K));
     t.begin(TC_FRAME);
-    hipLaunchKernelGGL(fc128_kernel<FC_GRAD>, dim3(grid), dim3(1024), kFc128Smem, s, A);
+    const hipError_t e = A.stream ? launch_fc128_nt<FC_GRAD, true>(A, grid, s) : launch_fc128_nt<FC_GRAD, false>(A, grid, s);
     t.end(TC_FRAME);
     *blocks_used = grid;
-    return hipGetLastError();
+    return e;
 }
 
 __global__ void __launch_bounds__(1024) batch_fc128_kernel(const FrameArgs* __restrict__ D,
@@ -712,7 +747,10 @@ __global__ void __launch_bounds__(1024) batch_fc128_kernel(const FrameArgs* __re
         const FrameArgs A = D[w.x];
         const int G = fc128_groups(A.K);
         Fc128Op<FC_RAAR> op{nullptr, nullptr, 0.f};
-        for (int f = fc128_slot(w.y, G); f < A.K; f += G) fc128_frame<FC_RAAR>(A, f, lds, twl, op);
+        if (A.stream)
+            for (int f = fc128_slot(w.y, G); f < A.K; f += G) fc128_frame<FC_RAAR, true>(A, f, lds, twl, op);
+        else
+            for (int f = fc128_slot(w.y, G); f < A.K; f += G) fc128_frame<FC_RAAR, false>(A, f, lds, twl, op);
         const float s = block_sum(op.resid, red);
         if (threadIdx.x == 0) A.resid[w.y] = s;
     }
@@ -1352,6 +1390,7 @@ hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* 
 // The carry and the amplitudes are stored column-block-major (cb256), so the
 // column pass reads and writes one contiguous block per workgroup.
 // ---------------------------------------------------------------------------
+template <bool STREAM>
 __device__ float col_carry_item(const FrameArgs& A, int it, float2* lds, const float2* twl) {
     const int tid = opaque_tid();
     constexpr int M = 256;
@@ -1370,15 +1409,15 @@ __device__ float col_carry_item(const FrameArgs& A, int it, float2* lds, const f
         const int e0 = 2 * (tid + NT * k);
         const int y = e0 / CB, c = e0 % CB;
         float2 a0, a1;
-        ld2(A.stage + fb, y * M + cb * CB + c, a0, a1);
+        ld2t<STREAM>(A.stage + fb, y * M + cb * CB + c, a0, a1);
         lds[pidx(e0)] = a0;
         lds[pidx(e0 + 1)] = a1;
     }
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int e0 = 2 * (tid + NT * k);
-        ld2(A.u + blk, e0, uc[2 * k], uc[2 * k + 1]);
-        ac[k] = ldf2(A.a + blk, e0);
+        ld2t<STREAM>(A.u + blk, e0, uc[2 * k], uc[2 * k + 1]);
+        ac[k] = ldf2t<STREAM>(A.a + blk, e0);
     }
     __syncthreads();
     NoPost none;
@@ -1395,7 +1434,7 @@ __device__ float col_carry_item(const FrameArgs& A, int it, float2* lds, const f
         const float2 z0 = cadd(u0, cscale(lds[pidx(e0)], gm));
         const float2 z1 = cadd(u1, cscale(lds[pidx(e0 + 1)], gm));
         const float2 y0 = op.modulus(z0, av.x, true), y1 = op.modulus(z1, av.y, true);
-        st2(A.u + blk, e0, cadd(cscale(z0, b), cscale(y0, c1)), cadd(cscale(z1, b), cscale(y1, c1)));
+        st2t<STREAM>(A.u + blk, e0, cadd(cscale(z0, b), cscale(y0, c1)), cadd(cscale(z1, b), cscale(y1, c1)));
         lds[pidx(e0)] = csub(cscale(y0, 2.f), z0);
         lds[pidx(e0 + 1)] = csub(cscale(y1, 2.f), z1);
     }
@@ -1405,12 +1444,13 @@ __device__ float col_carry_item(const FrameArgs& A, int it, float2* lds, const f
     for (int k = 0; k < NP; ++k) {
         const int e0 = 2 * (tid + NT * k);
         const int y = e0 / CB, c = e0 % CB;
-        st2(A.stage + fb, y * M + cb * CB + c, lds[pidx(e0)], lds[pidx(e0 + 1)]);
+        st2t<STREAM>(A.stage + fb, y * M + cb * CB + c, lds[pidx(e0)], lds[pidx(e0 + 1)]);
     }
     __syncthreads();
     return op.resid;
 }
 
+template <bool NT>
 __global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
     using C = MP<256, 256>;
     extern __shared__ float2 smem[];
@@ -1420,7 +1460,7 @@ __global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
     for (int t = threadIdx.x; t < 256; t += C::NT) twl[t] = A.tw[t];
     const int items = A.K * C::NCB;
     for (int it = blockIdx.x; it < items; it += gridDim.x) {
-        const float s = block_sum(col_carry_item(A, it, lds, twl), red);
+        const float s = block_sum(col_carry_item<NT>(A, it, lds, twl), red);
         if (threadIdx.x == 0) A.resid[it] = s;
     }
 }
@@ -1661,7 +1701,8 @@ __global__ void __launch_bounds__(256) batch_carry_kernel(const FrameArgs* __res
         if constexpr (PHASE == 0) {
             if (A.gather) mp_row_fwd_item<256, FM_GATHER, 256>(A, w.y, lds, twl);
         } else if constexpr (PHASE == 1) {
-            const float s = block_sum(col_carry_item(A, w.y, lds, twl), red);
+            const float r = A.stream ? col_carry_item<true>(A, w.y, lds, twl) : col_carry_item<false>(A, w.y, lds, twl);
+            const float s = block_sum(r, red);
             if (threadIdx.x == 0) A.resid[w.y] = s;
         } else {
             strip_merge_item(A, SD[w.x], w.y, lds, twl, twl + 256);
@@ -1783,7 +1824,8 @@ hipError_t launch_col_carry_256(const FrameArgs& A, hipStream_t s, const Timer* 
     using C = MP<256, 256>;
     if (A.K <= 0) return hipSuccess;
     t.begin(TC_COLS, s);
-    hipLaunchKernelGGL(col_carry_kernel, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A);
+    if (A.stream) hipLaunchKernelGGL(col_carry_kernel<true>, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A);
+    else hipLaunchKernelGGL(col_carry_kernel<false>, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A);
     t.end(TC_COLS, s);
     return hipGetLastError();
 }

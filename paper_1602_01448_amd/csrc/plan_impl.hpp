@@ -71,6 +71,11 @@ struct sharp_plan_s {
     template <class T> T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
     bool carry_form() const { return (m == 128 || m == 256) && frame_launch == 2; }
     bool strip_form() const { return m == 256 && frame_launch == 2; }
+    // frame arrays (K m^2 complex values) larger than the GPU's last-level
+    // cache (256 MiB on this part) are read and written with streaming
+    // accesses; smaller ones stay cacheable, since a pass often finds them there
+    static constexpr size_t kLastLevelCache = size_t(256) << 20;
+    bool streams() const { return (size_t)K * m * m * sizeof(float2) > kLastLevelCache; }
     size_t frame_elems() const { return (size_t)K * m * m; }
     size_t obj_elems() const { return (size_t)nx * ny; }
 };

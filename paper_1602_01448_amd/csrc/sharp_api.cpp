@@ -334,6 +334,7 @@ FrameArgs sharp::frame_args(const sharp_plan_s& p) {
     A.gw_part = p.at<float2>(p.off.gwpart);
     A.g = p.g;
     A.beta = 0.75f;
+    A.stream = p.streams();
     return A;
 }
 
@@ -361,6 +362,7 @@ MergeArgs sharp::merge_args(const sharp_plan_s& p) {
     A.part = p.at<float4>(p.off.mpart);
     A.g = p.g;
     A.eps_D = p.opt.eps_D;
+    A.stream = p.streams();
     return A;
 }
 
@@ -836,6 +838,7 @@ extern "C" int sharp_get_plan_info(sharp_plan p, sharp_plan_info* info) {
     info->frame_launch = p->frame_launch;
     info->fft_block = p->fft_block;
     info->strip_rows = p->strip_form() ? p->SH : 0;
+    info->streaming = p->streams() ? 1 : 0;
     info->csr_nnz = (long long)p->tile_frames.size();
     info->iteration = p->iter;
     return SHARP_OK;

@@ -60,6 +60,7 @@ struct FrameArgs {
     float2* __restrict__ gw_part;       // per-block probe-gradient partials
     float g, beta;
     int gather;                         // batched m = 256 carry form: run the gather pass
+    int stream;                         // frame arrays exceed the last-level cache: streaming accesses
 };
 
 struct MergeArgs {
@@ -78,6 +79,7 @@ struct MergeArgs {
     float* __restrict__ Dinv_out;       // MK_DENS
     float4* __restrict__ part;          // split partials [tiles][split][T*T] (x2 for VU)
     float g, eps_D;
+    int stream;                         // as FrameArgs::stream
 };
 
 // Optional per-launch timing hook (HIP events recorded on the launch stream).

@@ -113,6 +113,22 @@ def test_small_frame_form_selection(L, m, kw, form):
     L.sharp_plan_destroy(h)
 
 
+@pytest.mark.parametrize("m,K,stream", [(128, 2048, 0), (128, 2049, 1), (256, 512, 0), (256, 513, 1), (64, 5000, 0)])
+def test_streaming_threshold(L, m, K, stream):
+    """Frame arrays of K m^2 complex values above 256 MiB (the last-level
+    cache) are moved with streaming accesses; at or below it, cached ones."""
+    from paper_1602_01448_amd._lib import SharpPlanInfo
+    n = m + 64
+    pos = [(i % 65, (i // 65) % 65) for i in range(K)]
+    st, h = _create(L, n, m, pos)
+    assert st == 0
+    info = SharpPlanInfo()
+    assert L.sharp_get_plan_info(h, ctypes.byref(info)) == 0
+    assert info.streaming == stream
+    assert info.csr_nnz > 0 and info.strip_rows == (1 if m == 256 else 0)   # fields after it read correctly
+    L.sharp_plan_destroy(h)
+
+
 def test_calls_before_workspace_are_not_ready(L):
     st, h = _create(L, 64, 32, [(0, 0), (8, 8)])
     assert st == 0

@@ -93,6 +93,35 @@ def test_batch_full_size_uneven_scans_bitwise():
         assert np.array_equal(to_host(p.object()), to_host(q.object())), s.name
 
 
+def test_batch_streaming_scan_bitwise():
+    """A 128^2 scan whose frame arrays exceed the last-level cache (streaming
+    accesses) next to a small one: batched = single, bit for bit."""
+    import torch
+
+    from paper_1602_01448_amd import Batch, Plan
+    rng = np.random.default_rng(7)
+    n, m = 128 + 45 * 10, 128
+    big = gen.Scan("big", n, m, gen.raster_positions(46, 10, n, m, jitter=2, rng=rng), gen.random_object(rng, n, n),
+                   gen.gaussian_probe(m, 24.0), rng.uniform(0, 1, (n, n)).astype(complex), None, 0.75, 3, 0, 1,
+                   False, None)
+    scans = [big, _small_scans()[3]]
+    single, batched = [], []
+    for s in scans:
+        obj, w = to_dev(c64(s.obj)), to_dev(c64(s.probe))
+        for lst in (single, batched):
+            p = Plan(s.n, s.n, s.m, s.positions)
+            p.set_data(p.simulate(obj, w)).set_probe(w).set_object(to_dev(c64(s.psi0)))
+            lst.append(p)
+    assert [p.info()["streaming"] for p in single] == [1, 0]
+    for p in single:
+        p.raar(3, 0.75)
+    Batch(batched).raar(3, 0.75)
+    torch.cuda.synchronize()
+    for s, p, q in zip(scans, single, batched):
+        assert np.array_equal(to_host(p.object()), to_host(q.object())), s.name
+        assert np.array_equal(p.metrics(), q.metrics()), s.name
+
+
 def test_batch_rejects_probe_refinement_and_unready_plans():
     from paper_1602_01448_amd import Batch, Plan, SharpError
     s = _small_scans()[1]
