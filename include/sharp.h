@@ -223,8 +223,8 @@ typedef struct sharp_plan_info {
     int tile, tiles_x, tiles_y, merge_split, grad_groups, frame_launch, fft_block;
     int strip_rows;           /* form 2: object rows per merge strip (0 in form 1) */
     int streaming;            /* 1: the frame arrays (K m^2 complex values) exceed the GPU's 256 MiB
-                                 last-level cache and the frame and merge passes use streaming
-                                 (nontemporal) loads and stores for them; 0: cached accesses */
+                                 last-level cache and the frame passes use streaming (nontemporal)
+                                 loads and stores for them; 0: cached accesses */
     long long csr_nnz;        /* (tile, frame) incidences */
     long long iteration;      /* iterations run since sharp_set_object */
 } sharp_plan_info;

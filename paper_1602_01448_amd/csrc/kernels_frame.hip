@@ -111,9 +111,9 @@ __device__ __forceinline__ void stf2(float* __restrict__ p, unsigned i, float a,
     *reinterpret_cast<float2*>(const_cast<char*>(byte_at(p, i, 4u))) = make_float2(a, b);
 }
 // Streaming forms (nontemporal hint) for arrays that a pass reads or writes
-// once (the carry, the amplitudes, the stage buffer, the merge input): when
-// these arrays are larger than the last-level cache, the carry passes move
-// measurably more bytes per second with them.
+// once (the carry, the amplitudes, the stage buffer, the merge input of the
+// large frames): when these arrays are larger than the last-level cache, the
+// carry passes move measurably more bytes per second with them.
 __device__ __forceinline__ void ld2s(const float2* __restrict__ p, unsigned i, float2& a, float2& b) {
     const sf4 t = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(byte_at(p, i, 8u)));
     a = make_float2(t.x, t.y);

@@ -50,9 +50,8 @@ __device__ __forceinline__ void merge_finalize(const MergeArgs& A, size_t idx, f
 
 // One (tile, frame chunk) of the merge: sums the chunk's frames in ascending
 // order into the tile's pixels, then finalises (one chunk) or stores the
-// chunk partial.  NT: the frames are read with streaming loads (plans whose
-// frame arrays exceed the last-level cache).
-template <int T, int KIND, bool NT = false>
+// chunk partial.
+template <int T, int KIND>
 __device__ __forceinline__ void merge_tile(const MergeArgs& A, int tile, int chunk) {
     using KT = KindTraits<KIND>;
     constexpr int PPT = T * T / 256;
@@ -94,12 +93,7 @@ __device__ __forceinline__ void merge_tile(const MergeArgs& A, int tile, int chu
                 const int wo = fy * M + fx;
                 va[q][k] = ua[q][k] = wa[q][k] = make_float2(0.f, 0.f);
                 if (in) {
-                    if constexpr (KT::V && NT) {   // read once: streaming (nontemporal) load
-                        const sf2 t = __builtin_nontemporal_load(reinterpret_cast<const sf2*>(A.v + o));
-                        va[q][k] = make_float2(t.x, t.y);
-                    } else if constexpr (KT::V) {
-                        va[q][k] = A.v[o];
-                    }
+                    if constexpr (KT::V) va[q][k] = A.v[o];
                     if constexpr (KT::U) {
                         ua[q][k] = A.u[o];
                         wa[q][k] = A.w[wo];
@@ -135,9 +129,16 @@ __device__ __forceinline__ void merge_tile(const MergeArgs& A, int tile, int chu
     }
 }
 
-template <int T, int KIND, bool NT>
+// Workgroups are dealt to the XCDs round-robin (b mod 8); xcd_order gives
+// each XCD a contiguous run of tiles instead, so that horizontally adjacent
+// tiles run on one XCD at about the same time: the 128-byte lines that a
+// frame row shares between two tiles are then fetched from HBM once and hit
+// that XCD's L2 for the second tile.
+__device__ __forceinline__ int xcd_order(int b, int G) { return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3); }
+
+template <int T, int KIND>
 __global__ void __launch_bounds__(256) merge_kernel(MergeArgs A) {
-    merge_tile<T, KIND, NT>(A, blockIdx.x, blockIdx.y);
+    merge_tile<T, KIND>(A, xcd_order(blockIdx.x, gridDim.x), blockIdx.y);
 }
 
 // Second merge pass: chunk partials of one tile added in chunk order.
@@ -175,8 +176,7 @@ __global__ void __launch_bounds__(256) merge_finish_kernel(MergeArgs A) {
 
 template <int T, int KIND>
 static hipError_t launch_merge_tk(const MergeArgs& A, int tiles, hipStream_t s) {
-    if (KIND == MK_V && A.stream) hipLaunchKernelGGL((merge_kernel<T, KIND, true>), dim3(tiles, A.split), dim3(256), 0, s, A);
-    else hipLaunchKernelGGL((merge_kernel<T, KIND, false>), dim3(tiles, A.split), dim3(256), 0, s, A);
+    hipLaunchKernelGGL((merge_kernel<T, KIND>), dim3(tiles, A.split), dim3(256), 0, s, A);
     if (A.split > 1) hipLaunchKernelGGL((merge_finish_kernel<T, KIND>), dim3(tiles), dim3(256), 0, s, A);
     return hipGetLastError();
 }
@@ -374,10 +374,12 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
 template <int T>
 __global__ void __launch_bounds__(256) batch_merge_kernel(const MergeArgs* __restrict__ D, const int4* __restrict__ items,
                                                           int n) {
+    // round-robin over the items: their costs differ between scans (frames
+    // per tile grow with (m / step)^2), and contiguous runs per XCD (as in
+    // merge_kernel) measured slower here
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
-        if (D[w.x].stream) merge_tile<T, MK_V, true>(D[w.x], w.y, w.z);
-        else merge_tile<T, MK_V, false>(D[w.x], w.y, w.z);
+        merge_tile<T, MK_V>(D[w.x], w.y, w.z);
     }
 }
 

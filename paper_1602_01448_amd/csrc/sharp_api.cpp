@@ -362,7 +362,6 @@ MergeArgs sharp::merge_args(const sharp_plan_s& p) {
     A.part = p.at<float4>(p.off.mpart);
     A.g = p.g;
     A.eps_D = p.opt.eps_D;
-    A.stream = p.streams();
     return A;
 }
 

@@ -79,7 +79,6 @@ struct MergeArgs {
     float* __restrict__ Dinv_out;       // MK_DENS
     float4* __restrict__ part;          // split partials [tiles][split][T*T] (x2 for VU)
     float g, eps_D;
-    int stream;                         // as FrameArgs::stream
 };
 
 // Optional per-launch timing hook (HIP events recorded on the launch stream).
