@@ -1148,16 +1148,34 @@ __global__ void __launch_bounds__(256) probe_partial_kernel(int M, int K, const 
     den[(size_t)c * MM + p] = d;
 }
 
+// Fixed-order sums over C chunk partials ([C][MM] arrays), 32 pixels per
+// 256-thread workgroup: thread (g, q) = (t / 32, t mod 32) adds chunks g,
+// g + 8, g + 16, ... of pixel q in ascending order (independent loads, all in
+// flight), then the eight partials of the pixel are added in g order.  The
+// order depends on C only, never on scheduling.
+constexpr int kSumPix = 32, kSumWays = 8;
+
 __global__ void __launch_bounds__(256) probe_finish_kernel(int MM, int chunks, const float2* __restrict__ num,
                                                            const float* __restrict__ den, float2* __restrict__ w_gat,
                                                            float2* __restrict__ w_cur) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= MM) return;
+    __shared__ float2 sn[kSumWays][kSumPix];
+    __shared__ float sd[kSumWays][kSumPix];
+    const int q = threadIdx.x % kSumPix, g = threadIdx.x / kSumPix;
+    const int p = blockIdx.x * kSumPix + q;
     float2 n = make_float2(0.f, 0.f);
     float d = 0.f;
-    for (int c = 0; c < chunks; ++c) {
-        n = cadd(n, num[(size_t)c * MM + p]);
-        d += den[(size_t)c * MM + p];
+    if (p < MM)
+        for (int c = g; c < chunks; c += kSumWays) {
+            n = cadd(n, num[(size_t)c * MM + p]);
+            d += den[(size_t)c * MM + p];
+        }
+    sn[g][q] = n;
+    sd[g][q] = d;
+    __syncthreads();
+    if (g != 0 || p >= MM) return;
+    for (int k = 1; k < kSumWays; ++k) {
+        n = cadd(n, sn[k][q]);
+        d += sd[k][q];
     }
     const float2 old = w_cur[p];
     w_gat[p] = old;
@@ -1250,11 +1268,17 @@ hipError_t launch_probe_center(float2* w, float2* tmp, int M, hipStream_t s) {
 
 __global__ void __launch_bounds__(256) gw_finish_kernel(int MM, int slots, const float2* __restrict__ part,
                                                         float2* __restrict__ gw) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= MM) return;
-    float2 s = make_float2(0.f, 0.f);
-    for (int c = 0; c < slots; ++c) s = cadd(s, part[(size_t)c * MM + p]);
-    gw[p] = s;
+    __shared__ float2 sp[kSumWays][kSumPix];   // same fixed order as probe_finish_kernel
+    const int q = threadIdx.x % kSumPix, g = threadIdx.x / kSumPix;
+    const int p = blockIdx.x * kSumPix + q;
+    float2 acc = make_float2(0.f, 0.f);
+    if (p < MM)
+        for (int c = g; c < slots; c += kSumWays) acc = cadd(acc, part[(size_t)c * MM + p]);
+    sp[g][q] = acc;
+    __syncthreads();
+    if (g != 0 || p >= MM) return;
+    for (int k = 1; k < kSumWays; ++k) acc = cadd(acc, sp[k][q]);
+    gw[p] = acc;
 }
 
 hipError_t launch_probe_partial(int M, int K, const int* pos, int nx, int ny, int periodic, const float2* u,
@@ -1268,13 +1292,13 @@ hipError_t launch_probe_partial(int M, int K, const int* pos, int nx, int ny, in
 
 hipError_t launch_probe_finish(int M, int chunks, const float2* num, const float* den, float2* w_gat, float2* w_cur,
                                hipStream_t s) {
-    hipLaunchKernelGGL(probe_finish_kernel, dim3((M * M + 255) / 256), dim3(256), 0, s, M * M, chunks, num, den,
-                       w_gat, w_cur);
+    hipLaunchKernelGGL(probe_finish_kernel, dim3((M * M + kSumPix - 1) / kSumPix), dim3(256), 0, s, M * M, chunks,
+                       num, den, w_gat, w_cur);
     return hipGetLastError();
 }
 
 hipError_t launch_gw_finish(int M, int slots, const float2* part, float2* gw, hipStream_t s) {
-    hipLaunchKernelGGL(gw_finish_kernel, dim3((M * M + 255) / 256), dim3(256), 0, s, M * M, slots, part, gw);
+    hipLaunchKernelGGL(gw_finish_kernel, dim3((M * M + kSumPix - 1) / kSumPix), dim3(256), 0, s, M * M, slots, part, gw);
     return hipGetLastError();
 }
 
