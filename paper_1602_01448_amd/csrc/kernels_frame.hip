@@ -1574,8 +1574,24 @@ __device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b,
 #pragma unroll
         for (int r = 0; r < 16; ++r) ww[r] = ldc(A.w, (unsigned)rec.y * M + j + 16 * r);
     };
+    // Memory requests complete in order among loads, but loads and stores are
+    // not ordered with each other, so waiting for a load while stores are in
+    // flight waits for the stores too.  The loop therefore issues everything
+    // early and consumes it a batch later: records two batches ahead, probe
+    // rows one batch ahead, and the transformed lines of a batch wait in their
+    // LDS slots until the next batch has used its probe rows, then are stored.
     int4 cur = strip_my_record(S, b, e, line);
+    int4 nxt = strip_my_record(S, b + FPB, e, line);
+    int4 held = make_int4(-1, 0, 0, 0);   // record of the lines waiting in LDS
     loadw(cur);
+    __builtin_amdgcn_s_waitcnt(0);        // nothing in flight when the loop starts
+    auto store_held = [&]() {
+        if (held.x >= 0) {
+            float2* dst = A.stage + (size_t)held.x * MM + (size_t)held.y * M;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) dst[j + 16 * q] = lds[pidx(line * M + j + 16 * q)];
+        }
+    };
     for (int i = b; i < e; i += FPB) {
         float2 v[16];
         const float2* prow = psi_rows + sr * nx;
@@ -1591,19 +1607,22 @@ __device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b,
                 v[r] = cmul(ww[r], prow[gx]);
             }
         }
-        line_stage1<1>(v, lds, line, j);
-        const int4 nxt = strip_my_record(S, i + FPB, e, line);
+        store_held();
         if (i + FPB < e) loadw(nxt);
+        const int4 after = strip_my_record(S, i + 2 * FPB, e, line);
+        line_sync();   // the held lines are read before stage 1 rewrites the slots
+        line_stage1<1>(v, lds, line, j);
         line_sync();
         line_stage2<1>(v, lds, line, j, tw);
-        if (cur.x >= 0) {
-            float2* dst = A.stage + (size_t)cur.x * MM + (size_t)cur.y * M;
+        line_sync();   // stage-2 inputs are read before the results take the slots
 #pragma unroll
-            for (int q = 0; q < 16; ++q) dst[j + 16 * q] = v[q];
-        }
-        line_sync();   // the line's LDS slots are rewritten by the next batch
+        for (int q = 0; q < 16; ++q) lds[pidx(line * M + j + 16 * q)] = v[q];
+        held = cur;
         cur = nxt;
+        nxt = after;
     }
+    line_sync();
+    store_held();
     __syncthreads();
 }
 
@@ -1628,20 +1647,31 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = src[16 * r];
     };
+    // records are fetched two batches ahead, so that the lines of the next
+    // batch can be requested at once (no wait for a record load in between)
     int4 mine = strip_my_record(S, b, e, line);
+    int4 mine_next = strip_my_record(S, b + FPB, e, line);
     int4 cur = strip_records(S, b, e, lane);
     load_line(mine);
     for (int i = b; i < e; i += FPB) {
         line_stage1<-1>(v, lds, line, j);
-        const int4 mine_next = strip_my_record(S, i + FPB, e, line);
-        const int4 next = strip_records(S, i + FPB, e, lane);
-        if (i + FPB < e) load_line(mine_next);   // next batch in flight during this one
-        float2 ww[16];                           // conj(w) is applied to the line here
+        // conj(w) of the line (applied below) is requested before the next
+        // batch's lines: memory requests complete in order, so waiting for it
+        // then leaves the next batch in flight
+        float2 ww[16];
         {
             const float2* wrow = A.w + (unsigned)mine.y * M + j;
 #pragma unroll
             for (int q = 0; q < 16; ++q) ww[q] = wrow[16 * q];
         }
+        __builtin_amdgcn_sched_barrier(0);       // keeps that order
+        // next batch in flight during this one; requested unconditionally (past
+        // the last batch the record is absent and frame 0's row 0 is read and
+        // not used), so the count of requests in flight does not depend on the
+        // branch and the wait for conj(w) stays partial
+        load_line(mine_next);
+        const int4 mine_after = strip_my_record(S, i + 2 * FPB, e, line);
+        const int4 next = strip_records(S, i + FPB, e, lane);
         line_sync();
         {
             // a thread reads and writes the same 16 elements of its line here
@@ -1678,6 +1708,7 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
         }
         __syncthreads();
         mine = mine_next;
+        mine_next = mine_after;
         cur = next;
     }
     for (int sr = 0; sr < SH; ++sr) {
