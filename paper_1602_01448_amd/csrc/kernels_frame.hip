@@ -309,7 +309,11 @@ __device__ __forceinline__ void fg_group(const FrameArgs& A, int grp, float2* ld
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int e0 = 2 * (tid + NT * k);
-        const int f = e0 / MM, rem = e0 % MM, y = rem / M, x = rem % M;
+        // with m^2 >= 2 NT the frame of pair k is (2 NT k) / m^2 for every
+        // thread (2 tid < 2 NT <= m^2): uniform, so its position is loaded once
+        // through the scalar cache instead of per thread
+        const int f = (MM >= 2 * NT) ? (2 * NT * k) / MM : e0 / MM;
+        const int rem = e0 - f * MM, y = rem / M, x = rem % M;
         const int frame = f0 + f;
         z[2 * k] = z[2 * k + 1] = t[2 * k] = t[2 * k + 1] = make_float2(0.f, 0.f);
         if (frame < A.K)
@@ -635,12 +639,19 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = lds[sw128(row, t + 8 * r)];
         l128_planB<-1, false>(v, lds, twl, row, t);
+        // RAAR: the probe row is requested before the first store of v (a load
+        // issued after a store is waited for together with the store)
+        float2 wr[16];
+        if constexpr (MODE == FC_RAAR) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ld2(A.w, (unsigned)(row * M + 2 * t + 16 * q), wr[2 * q], wr[2 * q + 1]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const unsigned o = (unsigned)(row * M + 2 * t + 16 * q);
             if constexpr (MODE == FC_RAAR) {
-                float2 w0, w1;
-                ld2(A.w, o, w0, w1);
+                const float2 w0 = wr[2 * q], w1 = wr[2 * q + 1];
                 st2t<NT>(A.v + fb, o, cconjmul(w0, cscale(v[2 * q], inv_m)), cconjmul(w1, cscale(v[2 * q + 1], inv_m)));
             } else if constexpr (MODE == FC_GRAD) {
                 // T psi is gathered again (the object reads hit the caches)
