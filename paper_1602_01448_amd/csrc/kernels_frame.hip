@@ -529,9 +529,10 @@ __host__ __device__ int fc128_slot(int b, int G) { return (G & 7) ? b : (b & 7) 
 // amplitudes transposed, gathers psi; writes U' and v = conj(w) y).
 // FC_TO_SPACE: A.in (U transposed) -> A.out = F* U (natural layout).
 // FC_TO_CARRY: A.in (natural) -> A.out = F A.in (transposed).  FC_GRAD:
-// z = w T psi, r = 2 F*(Z - a sgn Z); writes v = conj(w) r and adds
-// conj(T psi) r to the workgroup's probe-gradient partial (its own slot of
-// A.gw_part; each thread updates the same 16 pixels every frame).  Ends with
+// z = w T psi, r = 2 F*(Z - a sgn Z); writes r itself to A.v (the merge
+// applies conj(w) for Q* r, and a chunked pass forms sum conj(T psi) r, so
+// no per-workgroup probe-gradient slot is read and rewritten per frame; those
+// slots are larger than the L2 and cost as much traffic as r).  Ends with
 // the row threads done with their rows: the next frame's first LDS writes
 // are made by the same threads, so frames need no barrier between them.
 template <int MODE, bool NT>
@@ -654,23 +655,7 @@ __device__ __forceinline__ void fc128_frame(const FrameArgs& A, int f, float2* l
                 const float2 w0 = wr[2 * q], w1 = wr[2 * q + 1];
                 st2t<NT>(A.v + fb, o, cconjmul(w0, cscale(v[2 * q], inv_m)), cconjmul(w1, cscale(v[2 * q + 1], inv_m)));
             } else if constexpr (MODE == FC_GRAD) {
-                // T psi is gathered again (the object reads hit the caches)
-                const int py = A.pos[2 * f], px = A.pos[2 * f + 1];
-                int gy = py + row, gx0 = px + 2 * t + 16 * q, gx1 = gx0 + 1;
-                if (A.periodic) {
-                    if (gy >= A.ny) gy -= A.ny;
-                    if (gx0 >= A.nx) gx0 -= A.nx;
-                    if (gx1 >= A.nx) gx1 -= A.nx;
-                }
-                const unsigned orow = (unsigned)gy * (unsigned)A.nx;
-                float2 w0, w1;
-                ld2(A.w, o, w0, w1);
-                const float2 r0 = cscale(v[2 * q], inv_m), r1 = cscale(v[2 * q + 1], inv_m);
-                st2t<NT>(A.v + fb, o, cconjmul(w0, r0), cconjmul(w1, r1));
-                float2* gp = A.gw_part + (size_t)blockIdx.x * MM;
-                float2 g0 = make_float2(0.f, 0.f), g1 = g0;
-                if (f != fc128_slot(blockIdx.x, gridDim.x)) ld2(gp, o, g0, g1);   // not the workgroup's first frame
-                st2(gp, o, cadd(g0, cconjmul(ldc(A.psi, orow + gx0), r0)), cadd(g1, cconjmul(ldc(A.psi, orow + gx1), r1)));
+                st2t<NT>(A.v + fb, o, cscale(v[2 * q], inv_m), cscale(v[2 * q + 1], inv_m));
             } else {
                 st2(A.out + fb, o, cscale(v[2 * q], inv_m), cscale(v[2 * q + 1], inv_m));
             }
@@ -1159,6 +1144,32 @@ __global__ void __launch_bounds__(256) probe_partial_kernel(int M, int K, const 
     den[(size_t)c * MM + p] = d;
 }
 
+// Probe gradient of the frame-residual form (Eq. (standardprobe)'s numerator
+// with r in place of z): per frame chunk, sum over its frames (ascending) of
+// conj(T psi) r at every frame pixel; chunk partials are then added in fixed
+// order by gw_finish_kernel.
+__global__ void __launch_bounds__(256) grad_probe_partial_kernel(int M, int K, const int* __restrict__ pos, int nx,
+                                                                 int ny, int periodic, const float2* __restrict__ r,
+                                                                 const float2* __restrict__ psi, int chunks,
+                                                                 float2* __restrict__ part) {
+    const int MM = M * M;
+    const int p = blockIdx.y * 256 + threadIdx.x;  // pixel index in the frame
+    if (p >= MM) return;
+    const int c = blockIdx.x;
+    const int f0 = (int)((long long)K * c / chunks), f1 = (int)((long long)K * (c + 1) / chunks);
+    const int y = p / M, x = p % M;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int f = f0; f < f1; ++f) {
+        int gy = pos[2 * f] + y, gx = pos[2 * f + 1] + x;
+        if (periodic) {
+            gy = wrap(gy, ny);
+            gx = wrap(gx, nx);
+        }
+        acc = cadd(acc, cconjmul(psi[(size_t)gy * nx + gx], r[(size_t)f * MM + p]));
+    }
+    part[(size_t)c * MM + p] = acc;
+}
+
 // Fixed-order sums over C chunk partials ([C][MM] arrays), 32 pixels per
 // 256-thread workgroup: thread (g, q) = (t / 32, t mod 32) adds chunks g,
 // g + 8, g + 16, ... of pixel q in ascending order (independent loads, all in
@@ -1298,6 +1309,14 @@ hipError_t launch_probe_partial(int M, int K, const int* pos, int nx, int ny, in
     dim3 grid(chunks, (M * M + 255) / 256);
     hipLaunchKernelGGL(probe_partial_kernel, grid, dim3(256), 0, s, M, K, pos, nx, ny, periodic, u, w, psi_v, psi_l,
                        beta, chunks, num, den);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_probe_partial(int M, int K, const int* pos, int nx, int ny, int periodic, const float2* r,
+                                     const float2* psi, int chunks, float2* part, hipStream_t s) {
+    dim3 grid(chunks, (M * M + 255) / 256);
+    hipLaunchKernelGGL(grad_probe_partial_kernel, grid, dim3(256), 0, s, M, K, pos, nx, ny, periodic, r, psi, chunks,
+                       part);
     return hipGetLastError();
 }
 

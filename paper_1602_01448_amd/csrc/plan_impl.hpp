@@ -75,6 +75,8 @@ struct sharp_plan_s {
     // cache (256 MiB on this part) are read and written with streaming
     // accesses; smaller ones stay cacheable, since a pass often finds them there
     static constexpr size_t kLastLevelCache = size_t(256) << 20;
+    // frame chunks of the probe-gradient pass of the m = 128 Fourier-carry form
+    int grad_chunks() const { return K < 128 ? K : 128; }
     bool streams() const { return (size_t)K * m * m * sizeof(float2) > kLastLevelCache; }
     size_t frame_elems() const { return (size_t)K * m * m; }
     size_t obj_elems() const { return (size_t)nx * ny; }

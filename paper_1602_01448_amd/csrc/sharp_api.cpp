@@ -198,7 +198,8 @@ static void layout(sharp_plan_s& p) {
     o.mpart = take(p.split > 1 ? (size_t)p.ntiles * p.split * p.T * p.T * 2 * sizeof(float4) : 0);
     o.pnum = take((size_t)p.probe_chunks * MM * sizeof(float2));
     o.pden = take((size_t)p.probe_chunks * MM * sizeof(float));
-    p.gw_slots = frame_partial_slots(p.m, FM_GRAD, p.m == 256 ? p.grad_groups : p.grad_groups);
+    p.gw_slots = frame_partial_slots(p.m, FM_GRAD, p.grad_groups);
+    if (p.m == 128 && p.carry_form()) p.gw_slots = std::max<size_t>(p.gw_slots, p.grad_chunks());
     o.gwpart = take(std::max<size_t>(p.gw_slots, 1) * MM * sizeof(float2));
     const size_t groups = (p.m == 256) ? (size_t)p.K * 32 : (size_t)(p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
     p.resid_cap = std::max<size_t>(groups, 2048);
@@ -655,18 +656,32 @@ extern "C" int sharp_grad(sharp_plan p, const void* d_psi, const void* d_w, floa
     A.w = (const float2*)d_w;
     A.w_g = (const float2*)d_w;
     int blocks = 0;
-    if (p->m == 128 && p->carry_form()) HIPCHK(launch_fc128_grad(A, p->grad_groups, s, p->tm(), &blocks));
+    // m = 128 Fourier-carry plans: the frame kernel writes r; Q* r applies
+    // conj(w) in the merge and the probe gradient is a chunked pass over r
+    const bool residual_form = p->m == 128 && p->carry_form();
+    if (residual_form) HIPCHK(launch_fc128_grad(A, p->grad_groups, s, p->tm(), &blocks));
     else HIPCHK(launch_frame(FM_GRAD, A, p->grad_groups, s, &blocks, p->tm()));
     HIPCHK(launch_loss(p->at<float>(p->off.resid), p->m == 256 ? p->K * 16 : blocks, d_loss, p->at<int>(p->off.flag), s));
     if (d_gpsi) {
         MergeArgs Mg = merge_args(*p);
         Mg.out = (float2*)d_gpsi;
+        if (residual_form) {
+            Mg.u = p->at<float2>(p->off.v);
+            Mg.w = (const float2*)d_w;
+        }
         if (p->timing) p->timer.begin(TC_MERGE);
-        HIPCHK(launch_merge(MK_RAW, Mg, p->ntiles, s));
+        HIPCHK(launch_merge(residual_form ? MK_RAWW : MK_RAW, Mg, p->ntiles, s));
         if (p->timing) p->timer.end(TC_MERGE);
     }
     if (d_gw) {
-        const int slots = frame_partial_slots(p->m, FM_GRAD, blocks);
+        if (residual_form) {
+            if (p->timing) p->timer.begin(TC_PROBE);
+            HIPCHK(launch_grad_probe_partial(p->m, p->K, p->at<int>(p->off.pos), p->nx, p->ny, p->opt.periodic,
+                                             p->at<float2>(p->off.v), (const float2*)d_psi, p->grad_chunks(),
+                                             p->at<float2>(p->off.gwpart), s));
+            if (p->timing) p->timer.end(TC_PROBE);
+        }
+        const int slots = residual_form ? p->grad_chunks() : frame_partial_slots(p->m, FM_GRAD, blocks);
         HIPCHK(launch_gw_finish(p->m, slots, p->at<float2>(p->off.gwpart), (float2*)d_gw, s));
     }
     return SHARP_OK;

@@ -102,6 +102,9 @@ hipError_t launch_probe_partial(int M, int K, const int* pos, int nx, int ny, in
 hipError_t launch_probe_finish(int M, int chunks, const float2* num, const float* den, float2* w_gat,
                                float2* w_cur, hipStream_t s);
 hipError_t launch_gw_finish(int M, int slots, const float2* part, float2* gw, hipStream_t s);
+// sum over frames of conj(T psi) r per frame pixel, in `chunks` frame-chunk partials (part: [chunks][M*M])
+hipError_t launch_grad_probe_partial(int M, int K, const int* pos, int nx, int ny, int periodic, const float2* r,
+                                     const float2* psi, int chunks, float2* part, hipStream_t s);
 
 // launchers (kernels_merge.hip)
 hipError_t launch_merge(int kind, const MergeArgs& a, int tiles, hipStream_t s);
