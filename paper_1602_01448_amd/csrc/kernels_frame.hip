@@ -1766,32 +1766,37 @@ __global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripA
 }
 
 // Batched form: phase 0 gather + row FFTs, 1 column pass with the carry,
-// 2 strip merge; items (scan, local item), identical arithmetic.
+// 2 strip merge; items (scan, local item), identical arithmetic.  One item
+// per workgroup (grid = items) and the scans' argument blocks by value, as in
+// the single-scan launches: a persistent loop over items and argument blocks
+// read from memory each kept about 20 more registers live (a wave per SIMD).
 template <int PHASE>
-__global__ void __launch_bounds__(256) batch_carry_kernel(const FrameArgs* __restrict__ D,
-                                                          const StripArgs* __restrict__ SD,
+__global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(const BatchCarryChunk CH,
+                                                          const FrameArgs* __restrict__ D,
                                                           const int2* __restrict__ items, int n) {
     using C = MP<256, 256>;
     extern __shared__ float2 smem[];
     __shared__ float red[4];
     float2* lds = smem;
     float2* twl = smem + (PHASE == 2 ? pidx(16 * 256) : C::LDS);
-    if (n <= 0) return;
-    const float2* tw = D[items[0].x].tw;
-    for (int t = threadIdx.x; t < 256; t += 256) twl[t] = tw[t];
+    const int it = blockIdx.x;
+    if (it >= n) return;
+    const int2 w = items[it];
+    const int slot = w.x - CH.base;
+    FrameArgs A = CH.a[slot];
+    A.g = D[w.x].g;             // set on the device between iterations
+    A.beta = D[w.x].beta;
+    A.gather = D[w.x].gather;
+    for (int t = threadIdx.x; t < 256; t += 256) twl[t] = A.tw[t];
     __syncthreads();
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int2 w = items[it];
-        const FrameArgs A = D[w.x];
-        if constexpr (PHASE == 0) {
-            if (A.gather) mp_row_fwd_item<256, FM_GATHER, 256>(A, w.y, lds, twl);
-        } else if constexpr (PHASE == 1) {
-            const float r = A.stream ? col_carry_item<true>(A, w.y, lds, twl) : col_carry_item<false>(A, w.y, lds, twl);
-            const float s = block_sum(r, red);
-            if (threadIdx.x == 0) A.resid[w.y] = s;
-        } else {
-            strip_merge_item(A, SD[w.x], w.y, lds, twl, twl + 256);
-        }
+    if constexpr (PHASE == 0) {
+        if (A.gather) mp_row_fwd_item<256, FM_GATHER, 256>(A, w.y, lds, twl);
+    } else if constexpr (PHASE == 1) {
+        const float r = A.stream ? col_carry_item<true>(A, w.y, lds, twl) : col_carry_item<false>(A, w.y, lds, twl);
+        const float s = block_sum(r, red);
+        if (threadIdx.x == 0) A.resid[w.y] = s;
+    } else {
+        strip_merge_item(A, CH.s[slot], w.y, lds, twl, twl + 256);
     }
 }
 
@@ -1811,12 +1816,12 @@ hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu) {
     return e;
 }
 
-hipError_t launch_batch_carry(int phase, const FrameArgs* D, const StripArgs* SD, const int2* items, int n, int grid,
+hipError_t launch_batch_carry(int phase, const BatchCarryChunk& C, const FrameArgs* D, const int2* items, int n,
                               size_t smem, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (phase == 0) hipLaunchKernelGGL(batch_carry_kernel<0>, dim3(grid), dim3(256), smem, s, D, SD, items, n);
-    else if (phase == 1) hipLaunchKernelGGL(batch_carry_kernel<1>, dim3(grid), dim3(256), smem, s, D, SD, items, n);
-    else hipLaunchKernelGGL(batch_carry_kernel<2>, dim3(grid), dim3(256), smem, s, D, SD, items, n);
+    if (phase == 0) hipLaunchKernelGGL(batch_carry_kernel<0>, dim3(n), dim3(256), smem, s, C, D, items, n);
+    else if (phase == 1) hipLaunchKernelGGL(batch_carry_kernel<1>, dim3(n), dim3(256), smem, s, C, D, items, n);
+    else hipLaunchKernelGGL(batch_carry_kernel<2>, dim3(n), dim3(256), smem, s, C, D, items, n);
     return hipGetLastError();
 }
 

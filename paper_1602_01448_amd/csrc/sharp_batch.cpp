@@ -43,10 +43,12 @@ struct sharp_batch_s {
     std::vector<int4> merge_items[3];     // per merge-tile class
     std::vector<int2> finish_items[3];
     std::vector<int2> carry_items[3];     // m = 256 Fourier-carry form: rows, columns, strips
+    std::vector<int> carry_first[3];      // first carry item of each scan (prefix, nplans + 1 entries)
+    std::vector<BatchCarryChunk> carry_chunks;   // argument blocks by value, kBatchChunk scans each
     std::vector<int2> fc_items;           // m = 128 Fourier-carry form: (scan, frame group)
     size_t carry_smem = 0;                // LDS of the strip phase (widest object)
     struct {
-        size_t fargs, margs, eps, sargs, fitems[5], mitems[3], fin[3], citems[3], fcitems, total;
+        size_t fargs, margs, eps, fitems[5], mitems[3], fin[3], citems[3], fcitems, total;
     } off{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -54,7 +56,6 @@ struct sharp_batch_s {
     hipStream_t own = nullptr;       // batch stream (graphs are captured and replayed here)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int grid_frame[5][3] = {};
-    int grid_carry[3] = {};
     int grid_fc = 1;
     int grid_merge = 0;
     std::map<std::pair<int, float>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
@@ -111,6 +112,11 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
             if (p->split > 1)
                 for (int t = 0; t < p->ntiles; ++t) b->finish_items[tc].push_back(make_int2(s, t));
         }
+        for (int c = 0; c < 3; ++c) {  // items are listed scan by scan
+            b->carry_first[c].assign(nplans + 1, 0);
+            for (const int2& w : b->carry_items[c]) ++b->carry_first[c][w.x + 1];
+            for (int s = 0; s < nplans; ++s) b->carry_first[c][s + 1] += b->carry_first[c][s];
+        }
         size_t cur = 0;
         auto take = [&](size_t bytes) {
             size_t at = cur;
@@ -120,7 +126,6 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         b->off.fargs = take(nplans * sizeof(FrameArgs));
         b->off.margs = take(nplans * sizeof(MergeArgs));
         b->off.eps = take(nplans * sizeof(EpsDesc));
-        b->off.sargs = take(nplans * sizeof(StripArgs));
         for (int c = 0; c < 3; ++c) b->off.citems[c] = take(b->carry_items[c].size() * sizeof(int2));
         b->off.fcitems = take(b->fc_items.size() * sizeof(int2));
         for (int c = 0; c < 5; ++c) b->off.fitems[c] = take(b->frame_items[c].size() * sizeof(int2));
@@ -180,11 +185,17 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),
                         p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
     }
+    b->carry_chunks.assign((n + kBatchChunk - 1) / kBatchChunk, BatchCarryChunk{});
+    for (int s = 0; s < n; ++s) {
+        BatchCarryChunk& C = b->carry_chunks[s / kBatchChunk];
+        C.base = s / kBatchChunk * kBatchChunk;
+        C.a[s % kBatchChunk] = fa[s];
+        C.s[s % kBatchChunk] = sa[s];
+    }
     hipStream_t st = b->own;
     HIPCHK(hipMemcpyAsync(b->ws + b->off.fargs, fa.data(), n * sizeof(FrameArgs), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->ws + b->off.margs, ma.data(), n * sizeof(MergeArgs), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->ws + b->off.eps, ea.data(), n * sizeof(EpsDesc), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(b->ws + b->off.sargs, sa.data(), n * sizeof(StripArgs), hipMemcpyHostToDevice, st));
     for (int c = 0; c < 3; ++c)
         if (!b->carry_items[c].empty())
             HIPCHK(hipMemcpyAsync(b->ws + b->off.citems[c], b->carry_items[c].data(),
@@ -215,11 +226,10 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
             HIPCHK(batch_frame_prepare(kM[c], ph, &per));
             b->grid_frame[c][ph] = std::max(1, per * cus);
         }
-    for (int ph = 0; ph < 3; ++ph) {
+    for (int ph = 0; ph < 3; ++ph) {  // LDS limits of the large-frame phases (grids: one item per workgroup)
         int per = 1;
         const size_t smem = ph == 2 ? b->carry_smem : carry_phase_smem();
         if (!b->carry_items[ph].empty()) HIPCHK(batch_carry_prepare(ph, smem, &per));
-        b->grid_carry[ph] = std::max(1, per * cus);
     }
     if (!b->fc_items.empty()) {
         int per = 1;
@@ -247,18 +257,25 @@ static int enqueue_iterations(sharp_batch_s& b, int n, float beta, hipStream_t s
             const int cnt = (int)b.fc_items.size();
             HIPCHK(launch_batch_fc128(D, b.at<int2>(b.off.fcitems), cnt, std::min(cnt, b.grid_fc), s));
         }
+        // large-frame phases: one launch per chunk of kBatchChunk scans that has items
+        auto carry = [&](int ph, size_t smem) -> int {
+            for (size_t c = 0; c < b.carry_chunks.size(); ++c) {
+                const int s0 = (int)c * kBatchChunk, s1 = std::min(ns, s0 + kBatchChunk);
+                const int i0 = b.carry_first[ph][s0], i1 = b.carry_first[ph][s1];
+                if (i1 > i0)
+                    HIPCHK(launch_batch_carry(ph, b.carry_chunks[c], D, b.at<int2>(b.off.citems[ph]) + i0, i1 - i0,
+                                              smem, s));
+            }
+            return SHARP_OK;
+        };
         for (int ph = l == 0 ? 0 : 1; ph < 2; ++ph) {  // later gathers come from the strip phase
-            const int cnt = (int)b.carry_items[ph].size();
-            if (cnt)
-                HIPCHK(launch_batch_carry(ph, D, b.at<StripArgs>(b.off.sargs), b.at<int2>(b.off.citems[ph]), cnt,
-                                          std::min(cnt, b.grid_carry[ph]), carry_phase_smem(), s));
+            const int st = carry(ph, carry_phase_smem());
+            if (st != SHARP_OK) return st;
         }
         HIPCHK(launch_batch_eps(E, D, ns, beta, s));
         {
-            const int cnt = (int)b.carry_items[2].size();
-            if (cnt)
-                HIPCHK(launch_batch_carry(2, D, b.at<StripArgs>(b.off.sargs), b.at<int2>(b.off.citems[2]), cnt,
-                                          std::min(cnt, b.grid_carry[2]), b.carry_smem, s));
+            const int st = carry(2, b.carry_smem);
+            if (st != SHARP_OK) return st;
         }
         for (int c = 0; c < 3; ++c)
             HIPCHK(launch_batch_merge(kT[c], DM, b.at<int4>(b.off.mitems[c]), (int)b.merge_items[c].size(),

@@ -149,7 +149,20 @@ hipError_t launch_fc128_grad(const FrameArgs& A, int grid, hipStream_t s, const 
 hipError_t batch_fc128_prepare(int* blocks_per_cu);
 hipError_t launch_batch_fc128(const FrameArgs* D, const int2* items, int n, int grid, hipStream_t s);
 hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu);
-hipError_t launch_batch_carry(int phase, const FrameArgs* D, const StripArgs* SD, const int2* items, int n, int grid,
+// The large-frame batch kernels take the argument blocks of up to kBatchChunk
+// scans by value (kernel arguments): pointers read from there are known to
+// address global memory, which keeps the kernels at the registers, and so at
+// the occupancy, of the single-scan launches.  Fields that change between
+// iterations on the device (g, beta, gather) are still read from D.
+constexpr int kBatchChunk = 12;
+struct BatchCarryChunk {
+    FrameArgs a[kBatchChunk];   // scans base .. base + kBatchChunk - 1
+    StripArgs s[kBatchChunk];
+    int base;
+};
+static_assert(sizeof(BatchCarryChunk) <= 4000, "kernel arguments are limited to 4 KiB");
+// items: (scan, item) of scans base .. base + kBatchChunk - 1, one workgroup each
+hipError_t launch_batch_carry(int phase, const BatchCarryChunk& C, const FrameArgs* D, const int2* items, int n,
                               size_t smem, hipStream_t s);
 size_t strip_smem_bytes(int SH, int nx);
 // m = 256 Fourier-carry form: gather + row transforms (first iteration only),
