@@ -429,6 +429,16 @@ __global__ void __launch_bounds__(FG<M>::NT) fg_kernel(FrameArgs A) {
 // ---------------------------------------------------------------------------
 static const Timer kNoTimer{};
 
+// Argument block of scan `scan` in a batch launch: the by-value copy with the
+// fields that change on the device between iterations taken from D.
+__device__ __forceinline__ FrameArgs batch_args(const BatchArgs& CH, const FrameArgs* __restrict__ D, int scan) {
+    FrameArgs A = CH.a[scan - CH.base];
+    A.g = D[scan].g;
+    A.beta = D[scan].beta;
+    A.gather = D[scan].gather;
+    return A;
+}
+
 // LDS position of frame element (y, x): XOR swizzle of the low five bits of
 // x, chosen so that the row-thread and column-thread patterns below (8 lines
 // of 8 threads per wavefront) hit distinct banks, except plan B's second-stage
@@ -728,28 +738,26 @@ hipError_t launch_fc128_grad(const FrameArgs& A, int grid, hipStream_t s, const 
     return e;
 }
 
-__global__ void __launch_bounds__(1024) batch_fc128_kernel(const FrameArgs* __restrict__ D,
+__global__ void __launch_bounds__(1024) batch_fc128_kernel(const BatchArgs CH, const FrameArgs* __restrict__ D,
                                                            const int2* __restrict__ items, int n) {
     extern __shared__ float2 smem[];
     __shared__ float red[16];
     float2* lds = smem;
     float2* twl = smem + 128 * 128;
-    if (n <= 0) return;
-    const float2* tw = D[items[0].x].tw;
-    for (int t = threadIdx.x; t < 128; t += 1024) twl[t] = tw[t];
+    const int it = blockIdx.x;
+    if (it >= n) return;
+    const int2 w = items[it];
+    const FrameArgs A = batch_args(CH, D, w.x);
+    for (int t = threadIdx.x; t < 128; t += 1024) twl[t] = A.tw[t];
     __syncthreads();
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int2 w = items[it];
-        const FrameArgs A = D[w.x];
-        const int G = fc128_groups(A.K);
-        Fc128Op<FC_RAAR> op{nullptr, nullptr, 0.f};
-        if (A.stream)
-            for (int f = fc128_slot(w.y, G); f < A.K; f += G) fc128_frame<FC_RAAR, true>(A, f, lds, twl, op);
-        else
-            for (int f = fc128_slot(w.y, G); f < A.K; f += G) fc128_frame<FC_RAAR, false>(A, f, lds, twl, op);
-        const float s = block_sum(op.resid, red);
-        if (threadIdx.x == 0) A.resid[w.y] = s;
-    }
+    const int G = fc128_groups(A.K);
+    Fc128Op<FC_RAAR> op{nullptr, nullptr, 0.f};
+    if (A.stream)
+        for (int f = fc128_slot(w.y, G); f < A.K; f += G) fc128_frame<FC_RAAR, true>(A, f, lds, twl, op);
+    else
+        for (int f = fc128_slot(w.y, G); f < A.K; f += G) fc128_frame<FC_RAAR, false>(A, f, lds, twl, op);
+    const float s = block_sum(op.resid, red);
+    if (threadIdx.x == 0) A.resid[w.y] = s;
 }
 
 hipError_t batch_fc128_prepare(int* blocks_per_cu) {
@@ -759,9 +767,9 @@ hipError_t batch_fc128_prepare(int* blocks_per_cu) {
     return e;
 }
 
-hipError_t launch_batch_fc128(const FrameArgs* D, const int2* items, int n, int grid, hipStream_t s) {
+hipError_t launch_batch_fc128(const BatchArgs& C, const FrameArgs* D, const int2* items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_fc128_kernel, dim3(grid), dim3(1024), kFc128Smem, s, D, items, n);
+    hipLaunchKernelGGL(batch_fc128_kernel, dim3(n), dim3(1024), kFc128Smem, s, C, D, items, n);
     return hipGetLastError();
 }
 
@@ -1340,48 +1348,44 @@ hipError_t launch_gw_finish(int M, int slots, const float2* part, float2* gw, hi
 // The grid is sized to the resident capacity and strides over the item list.
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ void __launch_bounds__(FG<M>::NT) batch_fg_kernel(const FrameArgs* __restrict__ D,
+__global__ void __launch_bounds__(FG<M>::NT) batch_fg_kernel(const BatchArgs CH, const FrameArgs* __restrict__ D,
                                                              const int2* __restrict__ items, int n) {
     using C = FG<M>;
     extern __shared__ float2 smem[];
     __shared__ float red[C::NT / 64];
     float2* lds = smem;
     float2* twl = smem + C::LDS;
-    if (n <= 0) return;
-    const float2* tw = D[items[0].x].tw;  // identical table for every scan of this frame size
-    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = tw[t];
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int2 w = items[it];
-        const FrameArgs A = D[w.x];
-        float resid = 0.f;
-        fg_group<M, FM_RAAR>(A, w.y, lds, twl, resid, nullptr);
-        const float s = block_sum(resid, red);
-        if (threadIdx.x == 0) A.resid[w.y] = s;
-    }
+    const int it = blockIdx.x;
+    if (it >= n) return;
+    const int2 w = items[it];
+    const FrameArgs A = batch_args(CH, D, w.x);
+    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = A.tw[t];
+    float resid = 0.f;
+    fg_group<M, FM_RAAR>(A, w.y, lds, twl, resid, nullptr);
+    const float s = block_sum(resid, red);
+    if (threadIdx.x == 0) A.resid[w.y] = s;
 }
 
 template <int M, int PHASE>
-__global__ void __launch_bounds__(256) batch_mp_kernel(const FrameArgs* __restrict__ D, const int2* __restrict__ items,
-                                                       int n) {
+__global__ void __launch_bounds__(256) batch_mp_kernel(const BatchArgs CH, const FrameArgs* __restrict__ D,
+                                                       const int2* __restrict__ items, int n) {
     using C = MP<M>;
     extern __shared__ float2 smem[];
     __shared__ float red[C::NT / 64];
     float2* lds = smem;
     float2* twl = smem + C::LDS;
-    if (n <= 0) return;
-    const float2* tw = D[items[0].x].tw;
-    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = tw[t];
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int2 w = items[it];
-        const FrameArgs A = D[w.x];
-        if constexpr (PHASE == 0) {
-            mp_row_fwd_item<M, FM_RAAR>(A, w.y, lds, twl);
-        } else if constexpr (PHASE == 1) {
-            const float s = block_sum(mp_col_item<M, FM_RAAR>(A, w.y, lds, twl), red);
-            if (threadIdx.x == 0) A.resid[w.y] = s;
-        } else {
-            mp_row_inv_item<M, FM_RAAR>(A, w.y, lds, twl, nullptr);
-        }
+    const int it = blockIdx.x;
+    if (it >= n) return;
+    const int2 w = items[it];
+    const FrameArgs A = batch_args(CH, D, w.x);
+    for (int t = threadIdx.x; t < M; t += C::NT) twl[t] = A.tw[t];
+    if constexpr (PHASE == 0) {
+        mp_row_fwd_item<M, FM_RAAR>(A, w.y, lds, twl);
+    } else if constexpr (PHASE == 1) {
+        const float s = block_sum(mp_col_item<M, FM_RAAR>(A, w.y, lds, twl), red);
+        if (threadIdx.x == 0) A.resid[w.y] = s;
+    } else {
+        mp_row_inv_item<M, FM_RAAR>(A, w.y, lds, twl, nullptr);
     }
 }
 
@@ -1415,18 +1419,19 @@ hipError_t batch_frame_prepare(int M, int phase, int* blocks_per_cu) {
     return e;
 }
 
-hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* items, int n, int grid,
+hipError_t launch_batch_frame(int M, int phase, const BatchArgs& C, const FrameArgs* D, const int2* items, int n,
                               hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    const dim3 g(n);
     switch (M) {
-        case 16: hipLaunchKernelGGL(batch_fg_kernel<16>, dim3(grid), dim3(FG<16>::NT), FG<16>::SMEM, s, D, items, n); break;
-        case 32: hipLaunchKernelGGL(batch_fg_kernel<32>, dim3(grid), dim3(FG<32>::NT), FG<32>::SMEM, s, D, items, n); break;
-        case 64: hipLaunchKernelGGL(batch_fg_kernel<64>, dim3(grid), dim3(FG<64>::NT), FG<64>::SMEM, s, D, items, n); break;
-        case 128: hipLaunchKernelGGL(batch_fg_kernel<128>, dim3(grid), dim3(FG<128>::NT), FG<128>::SMEM, s, D, items, n); break;
+        case 16: hipLaunchKernelGGL(batch_fg_kernel<16>, g, dim3(FG<16>::NT), FG<16>::SMEM, s, C, D, items, n); break;
+        case 32: hipLaunchKernelGGL(batch_fg_kernel<32>, g, dim3(FG<32>::NT), FG<32>::SMEM, s, C, D, items, n); break;
+        case 64: hipLaunchKernelGGL(batch_fg_kernel<64>, g, dim3(FG<64>::NT), FG<64>::SMEM, s, C, D, items, n); break;
+        case 128: hipLaunchKernelGGL(batch_fg_kernel<128>, g, dim3(FG<128>::NT), FG<128>::SMEM, s, C, D, items, n); break;
         case 256:
-            if (phase == 0) hipLaunchKernelGGL((batch_mp_kernel<256, 0>), dim3(grid), dim3(256), MP<256>::SMEM, s, D, items, n);
-            else if (phase == 1) hipLaunchKernelGGL((batch_mp_kernel<256, 1>), dim3(grid), dim3(256), MP<256>::SMEM, s, D, items, n);
-            else hipLaunchKernelGGL((batch_mp_kernel<256, 2>), dim3(grid), dim3(256), MP<256>::SMEM, s, D, items, n);
+            if (phase == 0) hipLaunchKernelGGL((batch_mp_kernel<256, 0>), g, dim3(256), MP<256>::SMEM, s, C, D, items, n);
+            else if (phase == 1) hipLaunchKernelGGL((batch_mp_kernel<256, 1>), g, dim3(256), MP<256>::SMEM, s, C, D, items, n);
+            else hipLaunchKernelGGL((batch_mp_kernel<256, 2>), g, dim3(256), MP<256>::SMEM, s, C, D, items, n);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1771,7 +1776,7 @@ __global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripA
 // the single-scan launches: a persistent loop over items and argument blocks
 // read from memory each kept about 20 more registers live (a wave per SIMD).
 template <int PHASE>
-__global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(const BatchCarryChunk CH,
+__global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(const BatchArgs CH,
                                                           const FrameArgs* __restrict__ D,
                                                           const int2* __restrict__ items, int n) {
     using C = MP<256, 256>;
@@ -1782,11 +1787,7 @@ __global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(co
     const int it = blockIdx.x;
     if (it >= n) return;
     const int2 w = items[it];
-    const int slot = w.x - CH.base;
-    FrameArgs A = CH.a[slot];
-    A.g = D[w.x].g;             // set on the device between iterations
-    A.beta = D[w.x].beta;
-    A.gather = D[w.x].gather;
+    const FrameArgs A = batch_args(CH, D, w.x);
     for (int t = threadIdx.x; t < 256; t += 256) twl[t] = A.tw[t];
     __syncthreads();
     if constexpr (PHASE == 0) {
@@ -1796,7 +1797,7 @@ __global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(co
         const float s = block_sum(r, red);
         if (threadIdx.x == 0) A.resid[w.y] = s;
     } else {
-        strip_merge_item(A, CH.s[slot], w.y, lds, twl, twl + 256);
+        strip_merge_item(A, CH.s[w.x - CH.base], w.y, lds, twl, twl + 256);
     }
 }
 
@@ -1816,7 +1817,7 @@ hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu) {
     return e;
 }
 
-hipError_t launch_batch_carry(int phase, const BatchCarryChunk& C, const FrameArgs* D, const int2* items, int n,
+hipError_t launch_batch_carry(int phase, const BatchArgs& C, const FrameArgs* D, const int2* items, int n,
                               size_t smem, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (phase == 0) hipLaunchKernelGGL(batch_carry_kernel<0>, dim3(n), dim3(256), smem, s, C, D, items, n);

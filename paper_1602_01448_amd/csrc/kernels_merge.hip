@@ -372,43 +372,41 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
 // Batched merge and residual reduction over a table of scans
 // ---------------------------------------------------------------------------
 template <int T>
-__global__ void __launch_bounds__(256) batch_merge_kernel(const MergeArgs* __restrict__ D, const int4* __restrict__ items,
+__global__ void __launch_bounds__(256) batch_merge_kernel(const BatchMergeArgs CH, const int4* __restrict__ items,
                                                           int n) {
-    // round-robin over the items: their costs differ between scans (frames
-    // per tile grow with (m / step)^2), and contiguous runs per XCD (as in
-    // merge_kernel) measured slower here
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int4 w = items[it];
-        merge_tile<T, MK_V>(D[w.x], w.y, w.z);
-    }
+    // one item per workgroup, dealt round-robin: item costs differ between
+    // scans (frames per tile grow with (m / step)^2), and contiguous runs per
+    // XCD (as in merge_kernel) measured slower here
+    const int it = blockIdx.x;
+    if (it >= n) return;
+    const int4 w = items[it];
+    merge_tile<T, MK_V>(CH.a[w.x - CH.base], w.y, w.z);
 }
 
 template <int T>
-__global__ void __launch_bounds__(256) batch_merge_finish_kernel(const MergeArgs* __restrict__ D,
+__global__ void __launch_bounds__(256) batch_merge_finish_kernel(const BatchMergeArgs CH,
                                                                  const int2* __restrict__ items, int n) {
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int2 w = items[it];
-        merge_finish_tile<T, MK_V>(D[w.x], w.y);
-    }
+    const int it = blockIdx.x;
+    if (it >= n) return;
+    const int2 w = items[it];
+    merge_finish_tile<T, MK_V>(CH.a[w.x - CH.base], w.y);
 }
 
-hipError_t launch_batch_merge(int T, const MergeArgs* D, const int4* items, int n, const int2* fin, int nfin,
-                              int grid, hipStream_t s) {
+hipError_t launch_batch_merge(int T, const BatchMergeArgs& C, const int4* items, int n, const int2* fin, int nfin,
+                              hipStream_t s) {
     if (n > 0) {
-        const int g = std::min(n, grid);
         switch (T) {
-            case 16: hipLaunchKernelGGL(batch_merge_kernel<16>, dim3(g), dim3(256), 0, s, D, items, n); break;
-            case 32: hipLaunchKernelGGL(batch_merge_kernel<32>, dim3(g), dim3(256), 0, s, D, items, n); break;
-            case 64: hipLaunchKernelGGL(batch_merge_kernel<64>, dim3(g), dim3(256), 0, s, D, items, n); break;
+            case 16: hipLaunchKernelGGL(batch_merge_kernel<16>, dim3(n), dim3(256), 0, s, C, items, n); break;
+            case 32: hipLaunchKernelGGL(batch_merge_kernel<32>, dim3(n), dim3(256), 0, s, C, items, n); break;
+            case 64: hipLaunchKernelGGL(batch_merge_kernel<64>, dim3(n), dim3(256), 0, s, C, items, n); break;
             default: return hipErrorInvalidValue;
         }
     }
     if (nfin > 0) {
-        const int g = std::min(nfin, grid);
         switch (T) {
-            case 16: hipLaunchKernelGGL(batch_merge_finish_kernel<16>, dim3(g), dim3(256), 0, s, D, fin, nfin); break;
-            case 32: hipLaunchKernelGGL(batch_merge_finish_kernel<32>, dim3(g), dim3(256), 0, s, D, fin, nfin); break;
-            case 64: hipLaunchKernelGGL(batch_merge_finish_kernel<64>, dim3(g), dim3(256), 0, s, D, fin, nfin); break;
+            case 16: hipLaunchKernelGGL(batch_merge_finish_kernel<16>, dim3(nfin), dim3(256), 0, s, C, fin, nfin); break;
+            case 32: hipLaunchKernelGGL(batch_merge_finish_kernel<32>, dim3(nfin), dim3(256), 0, s, C, fin, nfin); break;
+            case 64: hipLaunchKernelGGL(batch_merge_finish_kernel<64>, dim3(nfin), dim3(256), 0, s, C, fin, nfin); break;
             default: return hipErrorInvalidValue;
         }
     }

@@ -1,13 +1,15 @@
 // Batched RAAR over independent scans (plans) of uneven sizes.
 //
-// One iteration of every scan is one fixed launch sequence regardless of the
-// number of scans: per frame-size class a persistent frame kernel striding
-// over a (scan, item) work list, one residual reduction with a block per
-// scan, and per merge-tile class a persistent merge kernel over (scan, tile,
-// chunk) items.  n iterations are captured once into a hipGraph (keyed by n
-// and beta) and replayed on the batch's own stream, which is ordered after
-// the caller's stream with events.  Work items run exactly the single-scan
-// arithmetic, so each scan's result equals its single-scan run bit for bit.
+// One iteration of every scan is one fixed launch sequence: per frame-size
+// class a frame kernel over a (scan, item) work list (one item per
+// workgroup), one residual reduction with a block per scan, and per
+// merge-tile class a merge kernel over (scan, tile, chunk) items.  Kernels
+// take the argument blocks of up to kBatchChunk scans by value, so each class
+// is launched once per chunk of scans that has items of that class.  n
+// iterations are captured once into a hipGraph (keyed by n and beta) and
+// replayed on the batch's own stream, which is ordered after the caller's
+// stream with events.  Work items run exactly the single-scan arithmetic, so
+// each scan's result equals its single-scan run bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,21 +45,20 @@ struct sharp_batch_s {
     std::vector<int4> merge_items[3];     // per merge-tile class
     std::vector<int2> finish_items[3];
     std::vector<int2> carry_items[3];     // m = 256 Fourier-carry form: rows, columns, strips
-    std::vector<int> carry_first[3];      // first carry item of each scan (prefix, nplans + 1 entries)
-    std::vector<BatchCarryChunk> carry_chunks;   // argument blocks by value, kBatchChunk scans each
+    // first item of each scan in every list (prefix sums, nplans + 1 entries)
+    std::vector<int> frame_first[5], merge_first[3], finish_first[3], carry_first[3], fc_first;
+    std::vector<BatchArgs> arg_chunks;          // argument blocks by value, kBatchChunk scans each
+    std::vector<BatchMergeArgs> merge_chunks;
     std::vector<int2> fc_items;           // m = 128 Fourier-carry form: (scan, frame group)
     size_t carry_smem = 0;                // LDS of the strip phase (widest object)
     struct {
-        size_t fargs, margs, eps, fitems[5], mitems[3], fin[3], citems[3], fcitems, total;
+        size_t fargs, eps, fitems[5], mitems[3], fin[3], citems[3], fcitems, total;
     } off{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t user = nullptr;      // caller's stream
     hipStream_t own = nullptr;       // batch stream (graphs are captured and replayed here)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    int grid_frame[5][3] = {};
-    int grid_fc = 1;
-    int grid_merge = 0;
     std::map<std::pair<int, float>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 
     ~sharp_batch_s() {
@@ -112,11 +113,20 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
             if (p->split > 1)
                 for (int t = 0; t < p->ntiles; ++t) b->finish_items[tc].push_back(make_int2(s, t));
         }
-        for (int c = 0; c < 3; ++c) {  // items are listed scan by scan
-            b->carry_first[c].assign(nplans + 1, 0);
-            for (const int2& w : b->carry_items[c]) ++b->carry_first[c][w.x + 1];
-            for (int s = 0; s < nplans; ++s) b->carry_first[c][s + 1] += b->carry_first[c][s];
+        // items are listed scan by scan: the items of scans s0 .. s1 - 1 are
+        // first[s0] .. first[s1] - 1
+        auto prefix = [&](const auto& items, std::vector<int>& first) {
+            first.assign(nplans + 1, 0);
+            for (const auto& w : items) ++first[w.x + 1];
+            for (int s = 0; s < nplans; ++s) first[s + 1] += first[s];
+        };
+        for (int c = 0; c < 5; ++c) prefix(b->frame_items[c], b->frame_first[c]);
+        for (int c = 0; c < 3; ++c) {
+            prefix(b->merge_items[c], b->merge_first[c]);
+            prefix(b->finish_items[c], b->finish_first[c]);
+            prefix(b->carry_items[c], b->carry_first[c]);
         }
+        prefix(b->fc_items, b->fc_first);
         size_t cur = 0;
         auto take = [&](size_t bytes) {
             size_t at = cur;
@@ -124,7 +134,6 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
             return at;
         };
         b->off.fargs = take(nplans * sizeof(FrameArgs));
-        b->off.margs = take(nplans * sizeof(MergeArgs));
         b->off.eps = take(nplans * sizeof(EpsDesc));
         for (int c = 0; c < 3; ++c) b->off.citems[c] = take(b->carry_items[c].size() * sizeof(int2));
         b->off.fcitems = take(b->fc_items.size() * sizeof(int2));
@@ -185,16 +194,18 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),
                         p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
     }
-    b->carry_chunks.assign((n + kBatchChunk - 1) / kBatchChunk, BatchCarryChunk{});
+    b->arg_chunks.assign((n + kBatchChunk - 1) / kBatchChunk, BatchArgs{});
+    b->merge_chunks.assign((n + kBatchChunk - 1) / kBatchChunk, BatchMergeArgs{});
     for (int s = 0; s < n; ++s) {
-        BatchCarryChunk& C = b->carry_chunks[s / kBatchChunk];
-        C.base = s / kBatchChunk * kBatchChunk;
+        BatchArgs& C = b->arg_chunks[s / kBatchChunk];
+        BatchMergeArgs& CM = b->merge_chunks[s / kBatchChunk];
+        C.base = CM.base = s / kBatchChunk * kBatchChunk;
         C.a[s % kBatchChunk] = fa[s];
         C.s[s % kBatchChunk] = sa[s];
+        CM.a[s % kBatchChunk] = ma[s];
     }
     hipStream_t st = b->own;
     HIPCHK(hipMemcpyAsync(b->ws + b->off.fargs, fa.data(), n * sizeof(FrameArgs), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(b->ws + b->off.margs, ma.data(), n * sizeof(MergeArgs), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->ws + b->off.eps, ea.data(), n * sizeof(EpsDesc), hipMemcpyHostToDevice, st));
     for (int c = 0; c < 3; ++c)
         if (!b->carry_items[c].empty())
@@ -216,71 +227,70 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
                                   b->finish_items[c].size() * sizeof(int2), hipMemcpyHostToDevice, st));
     }
     HIPCHK(hipStreamSynchronize(st));
-    // persistent grids: resident blocks per CU x CUs
-    int dev = 0, cus = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // LDS limits of the kernels (grids: one item per workgroup)
+    int per = 1;
     for (int c = 0; c < 5; ++c)
-        for (int ph = 0; ph < (kM[c] == 256 ? 3 : 1); ++ph) {
-            int per = 1;
-            HIPCHK(batch_frame_prepare(kM[c], ph, &per));
-            b->grid_frame[c][ph] = std::max(1, per * cus);
-        }
-    for (int ph = 0; ph < 3; ++ph) {  // LDS limits of the large-frame phases (grids: one item per workgroup)
-        int per = 1;
+        for (int ph = 0; ph < (kM[c] == 256 ? 3 : 1); ++ph) HIPCHK(batch_frame_prepare(kM[c], ph, &per));
+    for (int ph = 0; ph < 3; ++ph) {
         const size_t smem = ph == 2 ? b->carry_smem : carry_phase_smem();
         if (!b->carry_items[ph].empty()) HIPCHK(batch_carry_prepare(ph, smem, &per));
     }
-    if (!b->fc_items.empty()) {
-        int per = 1;
-        HIPCHK(batch_fc128_prepare(&per));
-        b->grid_fc = std::max(1, per * cus);
+    if (!b->fc_items.empty()) HIPCHK(batch_fc128_prepare(&per));
+    return SHARP_OK;
+}
+
+// One launch per chunk of kBatchChunk scans that has items in the list.
+template <class F>
+static int per_chunk(const sharp_batch_s& b, const std::vector<int>& first, F launch) {
+    const int ns = (int)b.plans.size();
+    for (int c = 0; c * kBatchChunk < ns; ++c) {
+        const int s0 = c * kBatchChunk, s1 = std::min(ns, s0 + kBatchChunk);
+        if (first[s1] > first[s0] && launch(c, first[s0], first[s1] - first[s0]) != hipSuccess) return SHARP_ERR_HIP;
     }
-    b->grid_merge = 8 * cus;
     return SHARP_OK;
 }
 
 static int enqueue_iterations(sharp_batch_s& b, int n, float beta, hipStream_t s) {
     FrameArgs* D = b.at<FrameArgs>(b.off.fargs);
-    const MergeArgs* DM = b.at<MergeArgs>(b.off.margs);
     EpsDesc* E = b.at<EpsDesc>(b.off.eps);
     const int ns = (int)b.plans.size();
+#define CHUNKS(first, launch)                          \
+    do {                                               \
+        const int st_ = per_chunk(b, first, launch);   \
+        if (st_ != SHARP_OK) return st_;               \
+    } while (0)
     for (int l = 0; l < n; ++l) {
         for (int c = 0; c < 5; ++c) {
-            const int cnt = (int)b.frame_items[c].size();
-            if (!cnt) continue;
             const int2* items = b.at<int2>(b.off.fitems[c]);
             for (int ph = 0; ph < (kM[c] == 256 ? 3 : 1); ++ph)
-                HIPCHK(launch_batch_frame(kM[c], ph, D, items, cnt, std::min(cnt, b.grid_frame[c][ph]), s));
+                CHUNKS(b.frame_first[c], [&](int k, int i0, int cnt) {
+                    return launch_batch_frame(kM[c], ph, b.arg_chunks[k], D, items + i0, cnt, s);
+                });
         }
-        if (!b.fc_items.empty()) {
-            const int cnt = (int)b.fc_items.size();
-            HIPCHK(launch_batch_fc128(D, b.at<int2>(b.off.fcitems), cnt, std::min(cnt, b.grid_fc), s));
-        }
-        // large-frame phases: one launch per chunk of kBatchChunk scans that has items
-        auto carry = [&](int ph, size_t smem) -> int {
-            for (size_t c = 0; c < b.carry_chunks.size(); ++c) {
-                const int s0 = (int)c * kBatchChunk, s1 = std::min(ns, s0 + kBatchChunk);
-                const int i0 = b.carry_first[ph][s0], i1 = b.carry_first[ph][s1];
-                if (i1 > i0)
-                    HIPCHK(launch_batch_carry(ph, b.carry_chunks[c], D, b.at<int2>(b.off.citems[ph]) + i0, i1 - i0,
-                                              smem, s));
-            }
-            return SHARP_OK;
-        };
-        for (int ph = l == 0 ? 0 : 1; ph < 2; ++ph) {  // later gathers come from the strip phase
-            const int st = carry(ph, carry_phase_smem());
-            if (st != SHARP_OK) return st;
-        }
+        CHUNKS(b.fc_first, [&](int k, int i0, int cnt) {
+            return launch_batch_fc128(b.arg_chunks[k], D, b.at<int2>(b.off.fcitems) + i0, cnt, s);
+        });
+        for (int ph = l == 0 ? 0 : 1; ph < 2; ++ph)  // later gathers come from the strip phase
+            CHUNKS(b.carry_first[ph], [&](int k, int i0, int cnt) {
+                return launch_batch_carry(ph, b.arg_chunks[k], D, b.at<int2>(b.off.citems[ph]) + i0, cnt,
+                                          carry_phase_smem(), s);
+            });
         HIPCHK(launch_batch_eps(E, D, ns, beta, s));
-        {
-            const int st = carry(2, b.carry_smem);
+        CHUNKS(b.carry_first[2], [&](int k, int i0, int cnt) {
+            return launch_batch_carry(2, b.arg_chunks[k], D, b.at<int2>(b.off.citems[2]) + i0, cnt, b.carry_smem, s);
+        });
+        for (int c = 0; c < 3; ++c) {
+            // a chunk's merge items, then its finish items (the chunk partials of the same scans)
+            const int st = per_chunk(b, b.merge_first[c], [&](int k, int i0, int cnt) {
+                const int s0 = k * kBatchChunk, s1 = std::min(ns, s0 + kBatchChunk);
+                const int f0 = b.finish_first[c][s0], f1 = b.finish_first[c][s1];
+                return launch_batch_merge(kT[c], b.merge_chunks[k], b.at<int4>(b.off.mitems[c]) + i0, cnt,
+                                          b.at<int2>(b.off.fin[c]) + f0, f1 - f0, s);
+            });
             if (st != SHARP_OK) return st;
         }
-        for (int c = 0; c < 3; ++c)
-            HIPCHK(launch_batch_merge(kT[c], DM, b.at<int4>(b.off.mitems[c]), (int)b.merge_items[c].size(),
-                                      b.at<int2>(b.off.fin[c]), (int)b.finish_items[c].size(), b.grid_merge, s));
     }
+#undef CHUNKS
     return SHARP_OK;
 }
 

@@ -147,23 +147,30 @@ hipError_t launch_probe_center(float2* w, float2* tmp, int M, hipStream_t s);
 // amplitude-loss gradient at m = 128 (carry-form plans, which hold the transposed amplitudes)
 hipError_t launch_fc128_grad(const FrameArgs& A, int grid, hipStream_t s, const Timer* t, int* blocks_used);
 hipError_t batch_fc128_prepare(int* blocks_per_cu);
-hipError_t launch_batch_fc128(const FrameArgs* D, const int2* items, int n, int grid, hipStream_t s);
 hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu);
-// The large-frame batch kernels take the argument blocks of up to kBatchChunk
-// scans by value (kernel arguments): pointers read from there are known to
-// address global memory, which keeps the kernels at the registers, and so at
-// the occupancy, of the single-scan launches.  Fields that change between
+// The batch kernels take the argument blocks of up to kBatchChunk scans by
+// value (kernel arguments): pointers read from there are known to address
+// global memory (read from device memory they are not, and every access
+// becomes a flat one), which keeps the kernels at the registers, occupancy and
+// instruction forms of the single-scan launches.  Fields that change between
 // iterations on the device (g, beta, gather) are still read from D.
 constexpr int kBatchChunk = 12;
-struct BatchCarryChunk {
+struct BatchArgs {
     FrameArgs a[kBatchChunk];   // scans base .. base + kBatchChunk - 1
     StripArgs s[kBatchChunk];
     int base;
 };
-static_assert(sizeof(BatchCarryChunk) <= 4000, "kernel arguments are limited to 4 KiB");
+static_assert(sizeof(BatchArgs) <= 4000, "kernel arguments are limited to 4 KiB");
+struct BatchMergeArgs {
+    MergeArgs a[kBatchChunk];   // scans base .. base + kBatchChunk - 1
+    int base;
+};
+static_assert(sizeof(BatchMergeArgs) <= 4000, "kernel arguments are limited to 4 KiB");
 // items: (scan, item) of scans base .. base + kBatchChunk - 1, one workgroup each
-hipError_t launch_batch_carry(int phase, const BatchCarryChunk& C, const FrameArgs* D, const int2* items, int n,
+hipError_t launch_batch_carry(int phase, const BatchArgs& C, const FrameArgs* D, const int2* items, int n,
                               size_t smem, hipStream_t s);
+// items: (scan, frame group slot) of the chunk's scans, one workgroup each
+hipError_t launch_batch_fc128(const BatchArgs& C, const FrameArgs* D, const int2* items, int n, hipStream_t s);
 size_t strip_smem_bytes(int SH, int nx);
 // m = 256 Fourier-carry form: gather + row transforms (first iteration only),
 // column pass over the K frames of A, strip pass over strips [s0, s1)
@@ -190,10 +197,12 @@ struct BatchBegin {
     int gather[kMaxBatch];  // m = 256 carry form: stage does not hold the first iteration's gather
 };
 hipError_t batch_frame_prepare(int M, int phase, int* blocks_per_cu);
-hipError_t launch_batch_frame(int M, int phase, const FrameArgs* D, const int2* items, int n, int grid,
+// items: (scan, frame group or pass block) of the chunk's scans, one workgroup each
+hipError_t launch_batch_frame(int M, int phase, const BatchArgs& C, const FrameArgs* D, const int2* items, int n,
                               hipStream_t s);
-hipError_t launch_batch_merge(int T, const MergeArgs* D, const int4* items, int n, const int2* fin, int nfin,
-                              int grid, hipStream_t s);
+// items (scan, tile, chunk) and finish items (scan, tile) of the chunk's scans, one workgroup each
+hipError_t launch_batch_merge(int T, const BatchMergeArgs& C, const int4* items, int n, const int2* fin, int nfin,
+                              hipStream_t s);
 hipError_t launch_batch_eps(EpsDesc* E, FrameArgs* D, int nscans, float beta, hipStream_t s);
 hipError_t launch_batch_begin(FrameArgs* D, EpsDesc* E, const BatchBegin& b, float beta, hipStream_t s);
 
