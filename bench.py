@@ -324,7 +324,7 @@ def main() -> int:
                     help="m=256 pass workgroup threads (0: tuned or library default)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
+        print(f"bench.py: the benchmark runs on exactly one GPU (asked for {args.gpus}); "
               "multi-GPU sharding is a design note only", file=sys.stderr)
         return 2
 
