@@ -18,8 +18,8 @@ GPU-based ptychographic solver", arXiv:1602.01448):
   * metrics eps_a, eps_Q, eps_Delta, eps_0: Eqs. (amplitudemetric),
     (overlapmetric), (stagnationmetric), (solutionmetric).
 
-Readings taken where the paper is silent, ambiguous or garbled (each is also
-listed in DESIGN.md):
+Readings taken where the paper is silent, ambiguous or garbled (the GPU path
+takes the same ones):
 
   R1  The printed RAAR update in the algorithm box carries beta(P_Q - I); that
       operator has eigenvalue 1 - 3 beta on the orthogonal complement of
