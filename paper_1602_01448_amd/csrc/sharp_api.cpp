@@ -139,9 +139,11 @@ static void build_strips(sharp_plan_s& p) {
 }
 
 static void choose_tuning(sharp_plan_s& p) {
-    // tile side: small objects use small tiles so that enough workgroups exist
+    // tile side: 32 while that still gives >= 1024 tiles (workgroups enough
+    // for the merge without a frame-chunk split and its finishing pass),
+    // else 16
     if (p.opt.tile) p.T = p.opt.tile;
-    else p.T = (std::min(p.nx, p.ny) <= 256) ? 16 : 32;
+    else p.T = ((p.nx + 31) / 32) * ((p.ny + 31) / 32) >= 1024 ? 32 : 16;
     build_csr(p);
     int maxf = 0;
     for (int t = 0; t < p.ntiles; ++t) maxf = std::max(maxf, p.tile_ptr[t + 1] - p.tile_ptr[t]);
