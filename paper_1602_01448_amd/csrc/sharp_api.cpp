@@ -527,7 +527,13 @@ static int one_iteration(sharp_plan_s& p, float beta) {
         HIPCHK(launch_frame(FM_RAAR, A, 0, s, &blocks, t));
     }
     if (p.gat_stale) {
-        HIPCHK(launch_copy(p.ws + p.off.w_gat, p.ws + p.off.w_cur, (size_t)p.m * p.m * sizeof(float2), s));
+        // the frames above were gathered with the probe before the last
+        // update; later gathers use the current one.  A probe iteration's
+        // update writes the gather probe itself (the probe it replaces, which
+        // is the current one) and nothing reads it before, so the copy is only
+        // needed when this iteration updates no probe.
+        if (!probe_due)
+            HIPCHK(launch_copy(p.ws + p.off.w_gat, p.ws + p.off.w_cur, (size_t)p.m * p.m * sizeof(float2), s));
         p.gat_stale = false;
     }
     if (t) t->begin(TC_REDUCE);
