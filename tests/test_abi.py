@@ -113,6 +113,19 @@ def test_small_frame_form_selection(L, m, kw, form):
     L.sharp_plan_destroy(h)
 
 
+@pytest.mark.parametrize("n,tile", [(300, 16), (512, 16), (993, 16), (1000, 32), (2048, 32)])
+def test_default_merge_tile(L, n, tile):
+    """Merge tiles of 32 while that still gives >= 1024 tiles, else 16."""
+    from paper_1602_01448_amd._lib import SharpPlanInfo
+    st, h = _create(L, n, 64, [(0, 0), (n - 64, n - 64)])
+    assert st == 0
+    info = SharpPlanInfo()
+    assert L.sharp_get_plan_info(h, ctypes.byref(info)) == 0
+    assert info.tile == tile
+    assert info.tiles_x == -(-n // tile)
+    L.sharp_plan_destroy(h)
+
+
 @pytest.mark.parametrize("m,K,stream", [(128, 2048, 0), (128, 2049, 1), (256, 512, 0), (256, 513, 1), (64, 5000, 0)])
 def test_streaming_threshold(L, m, K, stream):
     """Frame arrays of K m^2 complex values above 256 MiB (the last-level
