@@ -113,7 +113,7 @@ def test_small_frame_form_selection(L, m, kw, form):
     L.sharp_plan_destroy(h)
 
 
-@pytest.mark.parametrize("n,tile", [(300, 16), (512, 16), (993, 16), (1000, 32), (2048, 32)])
+@pytest.mark.parametrize("n,tile", [(300, 16), (512, 16), (992, 16), (993, 32), (2048, 32)])
 def test_default_merge_tile(L, n, tile):
     """Merge tiles of 32 while that still gives >= 1024 tiles, else 16."""
     from paper_1602_01448_amd._lib import SharpPlanInfo
