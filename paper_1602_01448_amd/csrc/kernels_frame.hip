@@ -359,12 +359,15 @@ __device__ __forceinline__ void fg_group(const FrameArgs& A, int grp, float2* ld
         if (frame >= A.K) continue;
         const float2 y0 = cscale(lds[pidx(e0)], inv_m), y1 = cscale(lds[pidx(e0 + 1)], inv_m);
         if constexpr (MODE == FM_RAAR) {
-            float2 w0, w1;
+            // z is formed again (carry + gathered object term, as in the
+            // prologue) instead of being held in registers across the four
+            // transforms: 32 registers fewer, a wave per SIMD more
+            float2 w0, w1, za, zb, ta, tb;
+            prologue2<MODE>(A, frame, rem / M, rem % M, fb, e0, rem, za, zb, ta, tb);
             ld2(A.w, rem, w0, w1);
             const float b = A.beta, c = 1.f - 2.f * A.beta;
-            st2(A.u + fb, e0, cadd(cscale(z[2 * k], b), cscale(y0, c)), cadd(cscale(z[2 * k + 1], b), cscale(y1, c)));
-            st2(A.v + fb, e0, cconjmul(w0, csub(cscale(y0, 2.f), z[2 * k])),
-                cconjmul(w1, csub(cscale(y1, 2.f), z[2 * k + 1])));
+            st2(A.u + fb, e0, cadd(cscale(za, b), cscale(y0, c)), cadd(cscale(zb, b), cscale(y1, c)));
+            st2(A.v + fb, e0, cconjmul(w0, csub(cscale(y0, 2.f), za)), cconjmul(w1, csub(cscale(y1, 2.f), zb)));
         } else if constexpr (MODE == FM_PA) {
             st2(A.out + fb, e0, y0, y1);
         } else if constexpr (MODE == FM_GRAD) {
@@ -393,13 +396,23 @@ __global__ void __launch_bounds__(FG<M>::NT) fg_kernel(FrameArgs A) {
     for (int t = threadIdx.x; t < M; t += NT) twl[t] = A.tw[t];
 
     float resid = 0.f;
+    if constexpr (MODE != FM_GRAD) {
+        // grid = groups: one group per workgroup (no loop, so nothing is
+        // hoisted across groups and held in registers)
+        fg_group<M, MODE>(A, blockIdx.x, lds, twl, resid, nullptr);
+        if constexpr (MODE == FM_RAAR || MODE == FM_PA) {
+            const float s = block_sum(resid, red);
+            if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
+        }
+        return;
+    }
+    // GRAD: grid may be smaller than the groups (probe-gradient slots)
     float2 gacc[2 * NP];
 #pragma unroll
     for (int i = 0; i < 2 * NP; ++i) gacc[i] = make_float2(0.f, 0.f);
-
     const int ngroups = (A.K + G - 1) / G;
     for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) fg_group<M, MODE>(A, grp, lds, twl, resid, gacc);
-    if constexpr (MODE == FM_RAAR || MODE == FM_PA || MODE == FM_GRAD) {
+    {
         const float s = block_sum(resid, red);
         if (threadIdx.x == 0) A.resid[blockIdx.x] = s;
     }
