@@ -47,11 +47,10 @@ takes the same ones):
       Fourier amplitudes a_w replace |F w| with sgn(0) := 1; when both are
       given the mask is used (the box tests for the mask first).
   R15 Centre-of-mass correction (algorithm step 7): the centroid c of |w|^2
-      over pixel indices (y, x) in 0..m-1 (no wrap); w is rolled circularly by
-      the integer s = floor(m/2 - c + 1/2) per axis, which puts the centroid
-      within half a pixel of the frame centre (m/2, m/2) without
-      interpolation.  The integer is decided in FP32 (as the GPU does): c is
-      formed from FP32 sums.
+      over pixel indices (y, x) in 0..m-1 (no wrap), formed in FP64 (the paper
+      states no precision); w is rolled circularly by the integer
+      s = floor(m/2 - c + 1/2) per axis, which puts the centroid within half a
+      pixel of the frame centre (m/2, m/2) without interpolation.
 """
 from __future__ import annotations
 
@@ -62,7 +61,7 @@ __all__ = [
     "extract", "Q", "Qstar", "illumination_density", "dplus",
     "forward_intensity", "sgn", "P_a", "P_Q",
     "raar_step", "raar", "object_update", "probe_update", "init_probe",
-    "probe_fourier_constraint", "probe_center_shift", "probe_center",
+    "probe_fourier_constraint", "probe_centroid", "probe_center_shift", "probe_center",
     "eps_a", "eps_Q", "eps_Delta", "eps_0", "amplitude_loss", "amplitude_grad",
 ]
 
@@ -219,22 +218,25 @@ def probe_fourier_constraint(w, mask=None, amplitudes=None):
     return w
 
 
+def probe_centroid(w):
+    """Centroid (cy, cx) of |w|^2 over the pixel indices 0..m-1 (R15), in
+    FP64; None when w is zero."""
+    p = np.abs(np.asarray(w, dtype=np.complex128)) ** 2
+    tot = p.sum()
+    if tot <= 0:
+        return None
+    idx = np.arange(p.shape[0], dtype=np.float64)
+    return float((p.sum(axis=1) * idx).sum() / tot), float((p.sum(axis=0) * idx).sum() / tot)
+
+
 def probe_center_shift(w):
     """Integer roll (sy, sx) that brings the |w|^2 centroid to the frame
-    centre (R15).  Sums in FP32, pixel by pixel in row-major order."""
-    m = w.shape[-1]
-    p = (np.abs(np.asarray(w, dtype=np.complex64)) ** 2).astype(np.float32)
-    tot, sy, sx = np.float32(0), np.float32(0), np.float32(0)
-    for y in range(m):
-        for x in range(m):
-            tot = np.float32(tot + p[y, x])
-            sy = np.float32(sy + np.float32(y) * p[y, x])
-            sx = np.float32(sx + np.float32(x) * p[y, x])
-    if tot <= 0:
+    centre: s = floor(m/2 - c + 1/2) per axis (R15)."""
+    c = probe_centroid(w)
+    if c is None:
         return 0, 0
-    cy, cx = np.float32(sy / tot), np.float32(sx / tot)
-    half = np.float32(m // 2)
-    return int(np.floor(np.float32(half - cy + np.float32(0.5)))), int(np.floor(np.float32(half - cx + np.float32(0.5))))
+    half = w.shape[-1] // 2
+    return int(np.floor(half - c[0] + 0.5)), int(np.floor(half - c[1] + 0.5))
 
 
 def probe_center(w):
@@ -296,12 +298,15 @@ def raar_step(z, beta, proj_a, proj_Q):
 
 def raar(I, positions, shape, m, n_iter, beta=0.75, psi0=None, w0=None,
          probe_every=0, probe_start=1, periodic=False, record_extra=False,
-         rng_init=None, probe_mask=None, probe_amplitudes=None, probe_center_com=False):
+         rng_init=None, probe_mask=None, probe_amplitudes=None, probe_center_com=False,
+         trace=None):
     """The reconstruction sequence of the algorithm box.
 
     Returns a dict with the object psi (step 6 of the last iteration), the
     probe w, the frames z, the per-iteration eps_a (measured on the z that
     enters the iteration) and, with ``record_extra``, eps_Q and eps_Delta.
+    ``trace``, a list, receives the |w|^2 centroid each centre-of-mass
+    correction starts from (a record only; the iteration does not read it).
     """
     I = np.asarray(I, dtype=np.float64)
     a = np.sqrt(np.maximum(I, 0.0))                       # variance-stabilised amplitudes
@@ -325,6 +330,8 @@ def raar(I, positions, shape, m, n_iter, beta=0.75, psi0=None, w0=None,
             w = probe_update(z, psi, positions, periodic)                  # step 7
             w = probe_fourier_constraint(w, probe_mask, probe_amplitudes)
             if probe_center_com:
+                if trace is not None:
+                    trace.append(probe_centroid(w))
                 w = probe_center(w)
             D = illumination_density(w, positions, shape, periodic)
     return {"psi": psi, "w": w, "z": z, **{k: np.array(v) for k, v in hist.items()}}

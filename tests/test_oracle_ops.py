@@ -213,3 +213,75 @@ def test_eps_a_residual_identity(rng):
     a = rng.uniform(0, 1, (3, m, m))
     ref = np.linalg.norm(np.abs(np.fft.ifft2(z, norm="ortho")) - a) / np.linalg.norm(a)
     assert abs(O.eps_a(z, a) - ref) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# eps_Q and eps_Delta (Eqs. (overlapmetric), (stagnationmetric))
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m,positions,periodic", CASES)
+def test_eps_Q_against_dense_projector(rng, n, m, positions, periodic):
+    """||(P_Q - I) z|| / ||a|| with P_Q = M pinv(M) for the entry-by-entry
+    matrix M of Q (a textbook projector, not the oracle's P_Q); the
+    normaliser is ||a|| (not ||z||) and the sign is P_Q - I (P_Q + I gives a
+    different value)."""
+    pos = np.array(positions, dtype=np.int32)
+    w = _crandn(rng, m, m)
+    z = _crandn(rng, len(pos), m, m)
+    a = rng.uniform(0.5, 2.0, (len(pos), m, m))
+    M = _dense_Q(w, pos, n, periodic)
+    resid = M @ (np.linalg.pinv(M) @ z.ravel()) - z.ravel()
+    ref = np.sqrt(np.sum(np.abs(resid) ** 2)) / np.sqrt(np.sum(a ** 2))
+    got = O.eps_Q(z, w, pos, (n, n), a, periodic)
+    assert abs(got - ref) < 1e-12 * ref
+    plus = M @ (np.linalg.pinv(M) @ z.ravel()) + z.ravel()
+    assert abs(got - np.linalg.norm(plus) / np.linalg.norm(a)) > 0.1 * ref
+    assert abs(O.eps_Q(z, w, pos, (n, n), 2.0 * a, periodic) - ref / 2) < 1e-12 * ref
+
+
+def test_eps_Q_vanishes_on_the_range_of_Q(rng):
+    n, m = 40, 16
+    pos = gen.raster_positions(4, 8, n, m)
+    w = gen.gaussian_probe(m, 4.0)
+    z = O.Q(_crandn(rng, n, n), w, pos)
+    a = np.abs(O.dft(z))
+    assert O.eps_Q(z, w, pos, (n, n), a) < 1e-14
+
+
+def test_eps_Delta_closed_forms(rng):
+    """z_new = z_old + c e_j (one element changed by c) with a = 2 everywhere:
+    eps_Delta = |c| / (2 sqrt(K m^2)); unchanged frames give 0."""
+    K, m = 5, 4
+    z_old = _crandn(rng, K, m, m)
+    a = np.full((K, m, m), 2.0)
+    z_new = z_old.copy()
+    z_new[3, 1, 2] += 3.0 - 4.0j
+    assert abs(O.eps_Delta(z_new, z_old, a) - 5.0 / (2.0 * np.sqrt(K * m * m))) < 1e-15
+    assert O.eps_Delta(z_old, z_old, a) == 0.0
+    assert abs(O.eps_Delta(z_new, z_old, 4.0 * a) - 5.0 / (8.0 * np.sqrt(K * m * m))) < 1e-15
+
+
+def test_recorded_extra_metrics_follow_the_iterates(rng):
+    """raar(record_extra) records, after iteration l, ||(P_Q - I) z^(l)|| and
+    ||z^(l) - z^(l-1)|| over ||a||, with z^(0) = Q psi0 (reading R5); checked
+    with the dense projector and the iterates of shorter runs."""
+    n, m, positions, periodic = CASES[0]
+    pos = np.array(positions, dtype=np.int32)
+    w = _crandn(rng, m, m)
+    psi = _crandn(rng, n, n)
+    psi0 = _crandn(rng, n, n)
+    I = O.forward_intensity(psi, w, pos)
+    a = np.sqrt(I)
+    M = _dense_Q(w, pos, n, periodic)
+    P = M @ np.linalg.pinv(M)
+    L = 4
+    out = O.raar(I, pos, (n, n), m, L, 0.75, psi0=psi0, w0=w, record_extra=True)
+    z_prev = (M @ psi0.ravel()).reshape(len(pos), m, m)
+    na = np.sqrt(np.sum(a ** 2))
+    for l in range(1, L + 1):
+        z_l = O.raar(I, pos, (n, n), m, l, 0.75, psi0=psi0, w0=w)["z"]
+        eq = np.linalg.norm(P @ z_l.ravel() - z_l.ravel()) / na
+        ed = np.linalg.norm(z_l - z_prev) / na
+        assert abs(out["eps_Q"][l - 1] - eq) < 1e-10 * max(eq, 1e-300) + 1e-15
+        assert abs(out["eps_Delta"][l - 1] - ed) < 1e-12 * ed
+        z_prev = z_l
+    assert out["eps_Delta"][0] > 1e-3

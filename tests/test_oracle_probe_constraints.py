@@ -132,3 +132,31 @@ def test_raar_centering_keeps_the_probe_centred():
     p = np.abs(r["w"]) ** 2
     yy, xx = np.mgrid[0:m, 0:m]
     assert abs((p * yy).sum() / p.sum() - m // 2) <= 0.5 and abs((p * xx).sum() / p.sum() - m // 2) <= 0.5
+
+
+@pytest.mark.parametrize("p,q", [(0, 0), (3, 13), (15, 1)])
+def test_centroid_of_a_delta_is_its_pixel(p, q):
+    w = np.zeros((16, 16), complex)
+    w[p, q] = 0.5j
+    assert O.probe_centroid(w) == (float(p), float(q))
+    assert O.probe_centroid(np.zeros((16, 16), complex)) is None
+
+
+@pytest.mark.parametrize("delta,shift", [(1e-9, 1), (-1e-9, 0)])
+def test_center_decides_a_near_tie_in_double_precision(delta, shift):
+    """|w|^2 = 1 + delta at row 7 and 1 at row 8: the centroid is
+    7.5 - delta / (2 (2 + delta)), so the roll is 1 for delta > 0 and 0 for
+    delta < 0.  A single-precision sum (1 + 1e-9 rounds to 1) would see the
+    exact tie and take 1 both times."""
+    m = 16
+    w = np.zeros((m, m), complex)
+    w[7, 8] = np.sqrt(1.0 + delta)
+    w[8, 8] = 1.0
+    assert O.probe_center_shift(w) == (shift, 0)
+
+
+def test_raar_records_the_centroids_it_corrects():
+    n, m, pos, probe, I, psi0 = _scan()
+    trace = []
+    O.raar(I, pos, (n, n), m, 3, 0.75, psi0=psi0, probe_every=1, probe_center_com=True, trace=trace)
+    assert len(trace) == 3 and all(len(c) == 2 for c in trace)
