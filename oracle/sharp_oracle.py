@@ -28,7 +28,10 @@ takes the same ones):
       z <- [2 beta P_Q P_a + (1 - 2 beta) P_a + beta (I - P_Q)] z.
   R2  sgn(u) = u/|u| with sgn(0) := 1 (exact-zero test) inside P_a.
   R3  (Q*Q)^{-1} is applied as D^+ with D^+ = 1/D where D > 0 and 0 where
-      D = 0 (pixels no frame covers get psi = 0).
+      D = 0 (pixels no frame covers get psi = 0).  An optional threshold
+      eps_D >= 0 (a user option, 0 by default) widens the zero set to
+      D <= eps_D: P_Q then projects onto the frames of objects supported on
+      the pixels with D > eps_D.
   R4  Probe update: w = 0 where the denominator S* T |psi|^2 is 0.
   R5  z^(0) = Q psi^(0) (algorithm step 4); the "z^(0) = 0" next to the
       metrics is read as part of the eps_Delta definition only.
@@ -146,11 +149,11 @@ def illumination_density(w, positions, shape, periodic=False):
     return _scatter_add(np.ascontiguousarray(aw2), positions, shape, periodic).real
 
 
-def dplus(D):
-    """(Q*Q)^{-1} as used here: 1/D where D > 0, 0 elsewhere (R3)."""
+def dplus(D, eps_D=0.0):
+    """(Q*Q)^{-1} as used here: 1/D where D > eps_D, 0 elsewhere (R3)."""
     D = np.asarray(D, dtype=np.float64)
     out = np.zeros_like(D)
-    nz = D > 0
+    nz = D > eps_D
     out[nz] = 1.0 / D[nz]
     return out
 
@@ -178,21 +181,21 @@ def P_a(z, a):
     return idft(sgn(dft(z)) * np.asarray(a, dtype=np.float64))
 
 
-def P_Q(z, w, positions, shape, periodic=False, D=None):
+def P_Q(z, w, positions, shape, periodic=False, D=None, eps_D=0.0):
     """P_Q z = Q (Q*Q)^{-1} Q* z."""
     if D is None:
         D = illumination_density(w, positions, shape, periodic)
-    return Q(dplus(D) * Qstar(z, w, positions, shape, periodic), w, positions, periodic)
+    return Q(dplus(D, eps_D) * Qstar(z, w, positions, shape, periodic), w, positions, periodic)
 
 
 # ----------------------------------------------------------------------------
 # Updates (Eqs. (standardobject), (standardprobe))
 # ----------------------------------------------------------------------------
-def object_update(z, w, positions, shape, periodic=False, D=None):
-    """psi = Q* z / Q*Q  (0 where D = 0, R3)."""
+def object_update(z, w, positions, shape, periodic=False, D=None, eps_D=0.0):
+    """psi = Q* z / Q*Q  (0 where D = 0, or D <= eps_D, R3)."""
     if D is None:
         D = illumination_density(w, positions, shape, periodic)
-    return dplus(D) * Qstar(z, w, positions, shape, periodic)
+    return dplus(D, eps_D) * Qstar(z, w, positions, shape, periodic)
 
 
 def probe_update(z, psi, positions, periodic=False):
@@ -297,7 +300,7 @@ def raar_step(z, beta, proj_a, proj_Q):
 
 
 def raar(I, positions, shape, m, n_iter, beta=0.75, psi0=None, w0=None,
-         probe_every=0, probe_start=1, periodic=False, record_extra=False,
+         probe_every=0, probe_start=1, periodic=False, record_extra=False, eps_D=0.0,
          rng_init=None, probe_mask=None, probe_amplitudes=None, probe_center_com=False,
          trace=None):
     """The reconstruction sequence of the algorithm box.
@@ -316,13 +319,13 @@ def raar(I, positions, shape, m, n_iter, beta=0.75, psi0=None, w0=None,
     D = illumination_density(w, positions, shape, periodic)   # step 4
     z = Q(psi0, w, positions, periodic)
     hist = {"eps_a": [], "eps_Q": [], "eps_Delta": []}
-    psi = object_update(z, w, positions, shape, periodic, D)
+    psi = object_update(z, w, positions, shape, periodic, D, eps_D)
     for it in range(1, n_iter + 1):
         hist["eps_a"].append(eps_a(z, a))
         z_old = z
         z = raar_step(z, beta, lambda v: P_a(v, a),
-                      lambda v: P_Q(v, w, positions, shape, periodic, D))  # step 5
-        psi = object_update(z, w, positions, shape, periodic, D)          # step 6
+                      lambda v: P_Q(v, w, positions, shape, periodic, D, eps_D))  # step 5
+        psi = object_update(z, w, positions, shape, periodic, D, eps_D)          # step 6
         if record_extra:
             hist["eps_Q"].append(eps_Q(z, w, positions, shape, a, periodic))
             hist["eps_Delta"].append(eps_Delta(z, z_old, a))

@@ -285,3 +285,25 @@ def test_recorded_extra_metrics_follow_the_iterates(rng):
         assert abs(out["eps_Delta"][l - 1] - ed) < 1e-12 * ed
         z_prev = z_l
     assert out["eps_Delta"][0] > 1e-3
+
+
+@pytest.mark.parametrize("n,m,positions,periodic", CASES)
+def test_P_Q_with_density_threshold_is_the_restricted_projector(rng, n, m, positions, periodic):
+    """With the threshold eps_D the object update leaves the pixels with
+    D <= eps_D at 0, and P_Q is the orthogonal projector onto Q of objects
+    supported on D > eps_D: M_S pinv(M_S), M_S the columns of the dense Q
+    matrix for those pixels (reading R3)."""
+    pos = np.array(positions, dtype=np.int32)
+    w = _crandn(rng, m, m)
+    z = _crandn(rng, len(pos), m, m)
+    D = O.illumination_density(w, pos, (n, n), periodic)
+    eps = np.quantile(D[D > 0], 0.3)
+    S = (D > eps).ravel()
+    assert 0 < S.sum() < np.count_nonzero(D)
+    M = _dense_Q(w, pos, n, periodic)[:, S]
+    ref = M @ np.linalg.pinv(M) @ z.ravel()
+    got = O.P_Q(z, w, pos, (n, n), periodic, eps_D=eps).ravel()
+    assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
+    obj = O.object_update(z, w, pos, (n, n), periodic, eps_D=eps)
+    assert np.all(obj.ravel()[~S] == 0)
+    assert np.linalg.norm(obj.ravel()[S] - np.linalg.pinv(M) @ z.ravel()) < 1e-12 * np.linalg.norm(obj)
