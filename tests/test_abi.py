@@ -51,9 +51,10 @@ def _create(L, n, m, pos, **kw):
 
 
 def test_status_strings(L):
-    for s in range(-9, 1):
+    for s in range(-8, 1):
         assert len(L.sharp_status_string(s)) > 0
     assert L.sharp_status_string(-99) == b"unknown status"
+    assert L.sharp_status_string(-9) == b"unknown status"
 
 
 @pytest.mark.parametrize("m,expect", [(16, 0), (32, 0), (64, 0), (128, 0), (256, 0), (48, -2), (8, -2), (512, -2)])

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from helpers import c64, dweighted, to_dev, to_host
+from helpers import c64, check_object, to_dev, to_host
 from sharp_data import gen
 
 pytestmark = pytest.mark.gpu
@@ -66,7 +66,7 @@ def test_batch_matches_oracle():
         ref = O.raar(I.astype(np.float64), s.positions, (s.n, s.n), s.m, 5, 0.75, psi0=c64(s.psi0),
                      w0=c64(s.probe))
         D = O.illumination_density(s.probe, s.positions, (s.n, s.n))
-        assert dweighted(to_host(p.object()), ref["psi"], D) < 1e-4, s.name
+        check_object(to_host(p.object()), ref["psi"], D, 1e-4, where=s.name)
 
 
 def test_batch_full_size_uneven_scans_bitwise():
@@ -132,3 +132,34 @@ def test_batch_rejects_probe_refinement_and_unready_plans():
     q = Plan(s.n, s.n, s.m, s.positions)
     with pytest.raises(SharpError):
         Batch([q])
+
+
+def test_batch_refuses_a_plan_moved_to_another_workspace():
+    """A member plan given a new workspace after the batch took its pointers:
+    the batch returns NOT_READY without launching, and runs again, equal to
+    the single-scan run bit for bit, once its workspace is set again."""
+    import ctypes
+
+    import torch
+    from paper_1602_01448_amd import Batch, SharpError
+    from paper_1602_01448_amd._lib import check, lib
+    scans = _small_scans()[:3]
+    data = [_data(s) for s in scans]
+    plans = [_plan(s, I) for s, I in zip(scans, data)]
+    b = Batch(plans)
+    b.raar(2, 0.75)
+    p = plans[1]
+    nbytes = lib.sharp_workspace_bytes(p.handle)
+    p.workspace = torch.empty(nbytes, dtype=torch.uint8, device=p.device)
+    check(lib.sharp_set_workspace(p.handle, ctypes.c_void_p(p.workspace.data_ptr()), nbytes), "ws")
+    p.set_data(to_dev(data[1])).set_probe(to_dev(c64(scans[1].probe))).set_object(to_dev(c64(scans[1].psi0)))
+    before = [to_host(q.object()) for q in plans]
+    with pytest.raises(SharpError) as e:
+        b.raar(1, 0.75)
+    assert e.value.status == -4
+    torch.cuda.synchronize()
+    assert all(np.array_equal(to_host(q.object()), x) for q, x in zip(plans, before))
+    check(lib.sharp_batch_set_workspace(b._h, ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel()), "bws")
+    b.raar(3, 0.75)
+    single = _plan(scans[1], data[1]).raar(3, 0.75)
+    assert np.array_equal(to_host(single.object()), to_host(p.object()))

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from helpers import c64, rel, to_dev, to_host
+from helpers import c64, check_close, to_dev, to_host
 from sharp_data import gen
 
 pytestmark = pytest.mark.gpu
@@ -42,8 +42,8 @@ def test_dft_and_inverse(m, K, n):
     z = c64(_crandn(rng, K, m, m))
     F = to_host(p.apply("F", to_dev(z)))
     Fi = to_host(p.apply("FINV", to_dev(z)))
-    assert rel(F, O.dft(z)) < 2e-6
-    assert rel(Fi, O.idft(z)) < 2e-6
+    check_close(F, O.dft(z), 2e-6)
+    check_close(Fi, O.idft(z), 2e-6)
 
 
 @pytest.mark.parametrize("periodic", [False, True])
@@ -53,10 +53,10 @@ def test_Q_and_Qstar(m, K, n, periodic):
     p = _plan(n, m, pos, periodic=periodic)
     p.set_probe(to_dev(w))
     zq = to_host(p.apply("Q", to_dev(psi)))
-    assert rel(zq, O.Q(psi, w, pos, periodic)) < 1e-6
+    check_close(zq, O.Q(psi, w, pos, periodic), 1e-6)
     z = c64(_crandn(rng, K, m, m))
     qs = to_host(p.apply("QSTAR", to_dev(z)))
-    assert rel(qs, O.Qstar(z, w, pos, (n, n), periodic)) < 1e-6
+    check_close(qs, O.Qstar(z, w, pos, (n, n), periodic), 1e-6)
 
 
 @pytest.mark.parametrize("m,K,n", SIZES)
@@ -69,7 +69,7 @@ def test_data_projector(m, K, n):
     z = c64(_crandn(rng, K, m, m))
     y = to_host(p.apply("PA", to_dev(z)))
     ref = O.P_a(z, np.sqrt(I.astype(np.float64)))
-    assert rel(y, ref) < 1e-5
+    check_close(y, ref, 1e-5)
 
 
 @pytest.mark.parametrize("periodic", [False, True])
@@ -80,10 +80,10 @@ def test_overlap_projector_and_object_update(m, K, n, periodic):
     p.set_probe(to_dev(w))
     z = c64(_crandn(rng, K, m, m))
     y = to_host(p.apply("PQ", to_dev(z)))
-    assert rel(y, O.P_Q(z, w, pos, (n, n), periodic)) < 1e-5
+    check_close(y, O.P_Q(z, w, pos, (n, n), periodic), 1e-5)
     obj = to_host(p.apply("OBJECT", to_dev(z)))
     ref = O.object_update(z, w, pos, (n, n), periodic)
-    assert rel(obj, ref) < 1e-5
+    check_close(obj, ref, 1e-5)
     D = O.illumination_density(w, pos, (n, n), periodic)
     assert np.all(obj[D == 0] == 0)
 
@@ -96,7 +96,7 @@ def test_merge_tilings_agree(tile, split):
     p = _plan(n, m, pos, tile=tile, merge_split=split)
     p.set_probe(to_dev(w))
     z = c64(_crandn(rng, K, m, m))
-    assert rel(to_host(p.apply("PQ", to_dev(z))), O.P_Q(z, w, pos, (n, n))) < 1e-5
+    check_close(to_host(p.apply("PQ", to_dev(z))), O.P_Q(z, w, pos, (n, n)), 1e-5)
 
 
 @pytest.mark.parametrize("m,K,n", SIZES)
@@ -116,4 +116,4 @@ def test_initial_probe(m, K, n):
     p.set_data(to_dev(I))
     p.init_probe()
     got = to_host(p.probe())
-    assert rel(got, O.init_probe(I.astype(np.float64))) < 1e-5
+    check_close(got, O.init_probe(I.astype(np.float64)), 1e-5)
