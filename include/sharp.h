@@ -50,8 +50,7 @@ enum sharp_status {
     SHARP_ERR_WORKSPACE_TOO_SMALL = -5,
     SHARP_ERR_NONFINITE = -6,             /* NaN/Inf seen in data or in an iterate */
     SHARP_ERR_HIP = -7,                   /* a HIP runtime call failed */
-    SHARP_ERR_HOST_ALLOC = -8,            /* host metadata allocation failed */
-    SHARP_ERR_DEVICE_WAIT = -9            /* a bounded device-side wait expired (work left undone) */
+    SHARP_ERR_HOST_ALLOC = -8             /* host metadata allocation failed */
 };
 
 /* Static text for a status code (never NULL). */
@@ -209,7 +208,10 @@ int sharp_apply(sharp_plan plan, int op, const void* d_in, void* d_out);
  * complex64 [ny][nx], psi^(l) of the last probe-update iteration complex64
  * [ny][nx], current probe w complex64 [m][m], carry probe w_g complex64
  * [m][m], eps_a history float32 [4096], then a small header.  set_state
- * needs data to have been set; it rebuilds D from the restored probe.
+ * needs data to have been set; it rebuilds D from the restored probe.  It
+ * returns INVALID_ARG, before touching the plan, for a header of another
+ * geometry or with out-of-range fields (negative counters, a gather
+ * coefficient outside [0, 1] or not finite, flags other than 0 or 1).
  * ---------------------------------------------------------------------- */
 size_t sharp_state_bytes(sharp_plan plan);
 int sharp_get_state(sharp_plan plan, void* d_state);
@@ -251,6 +253,11 @@ int sharp_timing_read(sharp_plan plan, double* h_ms, long long* h_launches);
  * iteration, all scans together).  Each plan keeps its own state and must
  * have data, probe and object set; the plans' streams are ignored and the
  * batch's stream is used.  Plans with probe_every > 0 are rejected.
+ * The plans must outlive the batch.  sharp_batch_set_workspace records the
+ * workspace each plan has at that moment (its device pointers go into the
+ * batch's launch arguments): if a plan is given another workspace later
+ * (sharp_set_workspace), sharp_batch_raar_iterate returns NOT_READY before
+ * any launch until sharp_batch_set_workspace is called again.
  * ---------------------------------------------------------------------- */
 int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan* plans);
 void sharp_batch_destroy(sharp_batch batch);

@@ -19,7 +19,7 @@ STATUS = {
     0: "SHARP_OK", -1: "SHARP_ERR_INVALID_ARG", -2: "SHARP_ERR_UNSUPPORTED_SIZE",
     -3: "SHARP_ERR_POSITION_OUT_OF_RANGE", -4: "SHARP_ERR_NOT_READY",
     -5: "SHARP_ERR_WORKSPACE_TOO_SMALL", -6: "SHARP_ERR_NONFINITE", -7: "SHARP_ERR_HIP",
-    -8: "SHARP_ERR_HOST_ALLOC", -9: "SHARP_ERR_DEVICE_WAIT",
+    -8: "SHARP_ERR_HOST_ALLOC",
 }
 OPS = {"F": 0, "FINV": 1, "Q": 2, "QSTAR": 3, "PA": 4, "PQ": 5, "OBJECT": 6}
 

@@ -42,6 +42,7 @@ struct sharp_plan_s {
     size_t resid_cap = 0, gw_slots = 0;
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    unsigned long long ws_generation = 0;  // bumped by every sharp_set_workspace (batches check it)
     hipStream_t stream = nullptr;
     bool has_ws = false, has_data = false, has_probe = false, has_object = false;
     float g = 1.f;

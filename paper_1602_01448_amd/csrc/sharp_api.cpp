@@ -51,7 +51,6 @@ extern "C" const char* sharp_status_string(int s) {
         case SHARP_ERR_NONFINITE: return "non-finite value in data or iterate";
         case SHARP_ERR_HIP: return "HIP runtime error";
         case SHARP_ERR_HOST_ALLOC: return "host allocation failed";
-        case SHARP_ERR_DEVICE_WAIT: return "a bounded device-side wait expired; work was left undone";
     }
     return "unknown status";
 }
@@ -284,6 +283,7 @@ extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
     if (bytes < p->off.total) return SHARP_ERR_WORKSPACE_TOO_SMALL;
     p->ws = (char*)d;
     p->ws_bytes = bytes;
+    p->ws_generation++;
     p->has_ws = true;
     p->has_data = p->has_probe = p->has_object = false;
     p->pcons_kind = 0;
@@ -622,11 +622,10 @@ extern "C" int sharp_get_probe(sharp_plan p, void* d_out) {
 }
 
 static int read_flag(sharp_plan_s& p) {
-    int flag[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(flag, p.ws + p.off.flag, sizeof(flag), hipMemcpyDeviceToHost, p.stream));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, p.ws + p.off.flag, sizeof(flag), hipMemcpyDeviceToHost, p.stream));
     HIPCHK(hipStreamSynchronize(p.stream));
-    if (flag[1]) return SHARP_ERR_DEVICE_WAIT;
-    return flag[0] ? SHARP_ERR_NONFINITE : SHARP_OK;
+    return flag ? SHARP_ERR_NONFINITE : SHARP_OK;
 }
 
 extern "C" int sharp_sync(sharp_plan p) {
@@ -818,6 +817,11 @@ extern "C" int sharp_set_state(sharp_plan p, const void* d_state) {
     HIPCHK(hipMemcpyAsync(&h, d + L.header, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (h.magic != kMagic || h.nx != p->nx || h.ny != p->ny || h.m != p->m || h.K != p->K)
+        return SHARP_ERR_INVALID_ARG;
+    // the counters index the eps_a history and g scales the gather: reject a
+    // header whose fields no run of this library writes
+    if (h.iter < 0 || h.hist_count < 0 || h.hist_count > h.iter || !std::isfinite(h.g) || h.g < 0.f || h.g > 1.f ||
+        (h.gat_stale != 0 && h.gat_stale != 1) || (h.last_probe_updated != 0 && h.last_probe_updated != 1))
         return SHARP_ERR_INVALID_ARG;
     const size_t MM = (size_t)p->m * p->m;
     if (p->carry_form()) {

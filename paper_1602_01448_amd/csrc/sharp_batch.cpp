@@ -41,6 +41,7 @@ int t_class(int t) {
 
 struct sharp_batch_s {
     std::vector<sharp_plan_s*> plans;
+    std::vector<unsigned long long> ws_gen;  // each plan's workspace generation when the batch took its pointers
     std::vector<int2> frame_items[5];     // per frame-size class (m = 256: frame-space carry form)
     std::vector<int4> merge_items[3];     // per merge-tile class
     std::vector<int2> finish_items[3];
@@ -181,6 +182,11 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
     if (!b->ev_in) HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     if (!b->ev_out) HIPCHK(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
     const int n = (int)b->plans.size();
+    b->ws_gen.assign(n, 0);
+    for (int s = 0; s < n; ++s) {
+        if (!b->plans[s]->has_ws) return SHARP_ERR_NOT_READY;
+        b->ws_gen[s] = b->plans[s]->ws_generation;
+    }
     std::vector<FrameArgs> fa(n);
     std::vector<MergeArgs> ma(n);
     std::vector<EpsDesc> ea(n);
@@ -296,10 +302,16 @@ static int enqueue_iterations(sharp_batch_s& b, int n, float beta, hipStream_t s
 
 extern "C" int sharp_batch_raar_iterate(sharp_batch b, int n, float beta) {
     if (!b || n < 0 || !(beta > 0.f && beta <= 1.f)) return SHARP_ERR_INVALID_ARG;
-    if (!b->ws) return SHARP_ERR_NOT_READY;
-    for (sharp_plan_s* p : b->plans)
+    if (!b->ws || b->ws_gen.size() != b->plans.size()) return SHARP_ERR_NOT_READY;
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        const sharp_plan_s* p = b->plans[i];
+        // the launch arguments hold the workspace pointers recorded by
+        // sharp_batch_set_workspace: a plan moved to another workspace since
+        // would have its old buffers read and written
+        if (p->ws_generation != b->ws_gen[i]) return SHARP_ERR_NOT_READY;
         if (!p->has_ws || !p->has_data || !p->has_probe || !p->has_object || p->gat_stale)
             return SHARP_ERR_NOT_READY;
+    }
     if (n == 0) return SHARP_OK;
     BatchBegin bb{};
     bb.n = (int)b->plans.size();
