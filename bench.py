@@ -51,7 +51,7 @@ def algorithmic_bytes(K: int, m: int, n: int, form: int = 1) -> dict:
 
 def kernel_names(m: int, form: int) -> dict:
     if m == 256 and form == 2:
-        return {"frame": "mp_row_fwd<256, GATHER>", "cols": "col_carry_kernel", "merge": "strip_merge_kernel"}
+        return {"frame": "mp_row_fwd<256, GATHER>", "cols": "col_carry_kernel<true>", "merge": "strip_merge_kernel"}
     if m == 256:
         return {"frame": "mp_row_fwd<256, RAAR>", "cols": "mp_col<256, RAAR>", "frame_out": "mp_row_inv<256, RAAR>",
                 "merge": "merge_kernel<T, MK_V>"}
@@ -80,28 +80,121 @@ def gpu_workload(steps: int, warmup: int, timing: bool, fft_block: int = 0):
     plan.set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev))
     del obj, I
     plan.raar(warmup, s.beta)
-    torch.cuda.synchronize(dev)
+
+    def timed(n):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        t0.record()
+        for _ in range(n):
+            plan.raar(1, s.beta)
+        t1.record()
+        torch.cuda.synchronize(dev)
+        return t0.elapsed_time(t1)
+
+    # the headline region has no per-kernel events in it; a second region of
+    # the same length brackets every launch with events on the library's
+    # stream for the per-kernel durations
+    ms = timed(steps)
+    kt = {}
     if timing:
         plan.timing(True)
         plan.timing_read()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize(dev)
-    t0.record()
-    for _ in range(steps):
-        plan.raar(1, s.beta)
-    t1.record()
-    torch.cuda.synchronize(dev)
-    ms = t0.elapsed_time(t1)
-    kt = plan.timing_read() if timing else {}
-    plan.timing(False)
+        kt = {"region_ms": timed(steps), **plan.timing_read()}
+        plan.timing(False)
     eps = plan.metrics()
     return s, plan, ms, kt, eps
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _rate(frames: int, ms: float, alg_bytes: float) -> dict:
+    """frames/s and algorithmic GB/s (with its fraction of the HBM peak) for
+    `frames` frame-iterations moving `alg_bytes` in `ms` milliseconds."""
+    gbps = alg_bytes / (ms / 1e3) / 1e9
+    return {"frames_per_s": round(frames / (ms / 1e3), 1), "achieved_alg_GBps": round(gbps, 1),
+            "alg_frac_of_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+
+
+def plain_small_form(iters: int = 200) -> dict:
+    """The small plain workload: object 128^2, 169 frames of 32^2 (raster step
+    8), noiseless, known probe, beta 0.75.  Launch-latency bound: one
+    iteration moves 6.6 MB."""
+    import numpy as np
+    import torch
+
+    from paper_1602_01448_amd import Plan
+    from sharp_data import gen
+
+    dev = torch.device("cuda", 0)
+    s = gen.config_scan(1)
+    plan = Plan.tuned(s.n, s.n, s.m, s.positions, device=dev)
+    obj = torch.from_numpy(s.obj.astype(np.complex64)).to(dev)
+    w = torch.from_numpy(s.probe.astype(np.complex64)).to(dev)
+    plan.set_data(plan.simulate(obj, w)).set_probe(w)
+    plan.set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev)).raar(10, s.beta)
+    t0, t1 = _events()
+    torch.cuda.synchronize(dev)
+    t0.record()
+    plan.raar(iters, s.beta)
+    t1.record()
+    torch.cuda.synchronize(dev)
+    ms = t0.elapsed_time(t1) / iters
+    B = algorithmic_bytes(s.K, s.m, s.n)["iteration"]
+    return {"workload": "plain RAAR: object 128x128, 169 frames 32x32, noiseless, known probe",
+            "ms_per_iteration": round(ms, 5), **_rate(s.K, ms, B), "alg_bytes_per_iteration": B}
+
+
+def probe_refinement_form(iters: int = 50) -> dict:
+    """The probe-retrieval workload as configured: object 512^2 with smooth
+    phase, 841 frames of 64^2 (raster 16, jitter 2), circular-aperture probe
+    with defocus phase, Poisson noise at 1e6 photons per frame, probe from the
+    data, probe update every iteration (the configured run has 100
+    iterations; `iters` of them are timed after 5 untimed ones).  Algorithmic
+    bytes: the RAAR iteration plus 8 B per frame pixel and 24 B per object
+    pixel for the object output and the probe update."""
+    import numpy as np
+    import torch
+
+    from paper_1602_01448_amd import Plan
+    from sharp_data import gen
+
+    dev = torch.device("cuda", 0)
+    s = gen.config_scan(2)
+    plan = Plan.tuned(s.n, s.n, s.m, s.positions, probe_every=1, device=dev)
+    obj = torch.from_numpy(s.obj.astype(np.complex64)).to(dev)
+    w = torch.from_numpy(s.probe.astype(np.complex64)).to(dev)
+    I = plan.simulate(obj, w)
+    c = s.photons / (I.double().sum().item() / s.K)
+    g = torch.Generator(device=dev)
+    g.manual_seed(16022)
+    plan.set_data(torch.poisson(I * c, generator=g).float()).init_probe()
+    plan.set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev)).raar(5, s.beta)
+    t0, t1 = _events()
+    torch.cuda.synchronize(dev)
+    t0.record()
+    plan.raar(iters, s.beta)
+    t1.record()
+    torch.cuda.synchronize(dev)
+    ms = t0.elapsed_time(t1) / iters
+    fp, op = s.K * s.m * s.m, s.n * s.n
+    B = algorithmic_bytes(s.K, s.m, s.n)["iteration"] + 8 * fp + 24 * op
+    eps = plan.metrics()
+    return {"workload": "RAAR + probe refinement every iteration: object 512x512, 841 frames 64x64, "
+                        "Poisson 1e6 photons/frame, probe from the data",
+            "ms_per_iteration": round(ms, 5), **_rate(s.K, ms, B), "alg_bytes_per_iteration": B,
+            "eps_a_last": float(eps[-1])}
+
+
 def grad_form(reps: int = 10) -> dict:
     """Amplitude-loss gradient on the gradient workload (512^2 object, 1024
-    frames of 128^2): frames/s = K / (time of one sharp_grad call)."""
+    frames of 128^2): frames/s = K / (time of one sharp_grad call).
+    Algorithmic bytes per call: 20 B per frame pixel (amplitudes 4, residual
+    written 8 and read 8 by the merge) and 16 B per object pixel (object read,
+    gradient written)."""
     import numpy as np
     import torch
 
@@ -120,7 +213,7 @@ def grad_form(reps: int = 10) -> dict:
     for _ in range(3):
         plan.grad(tpsi, tw)
     torch.cuda.synchronize(dev)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0, t1 = _events()
     t0.record()
     for _ in range(reps):
         plan.grad(tpsi, tw)
@@ -129,15 +222,15 @@ def grad_form(reps: int = 10) -> dict:
     ms = t0.elapsed_time(t1) / reps
     fp = s.K * s.m * s.m
     alg = 20 * fp + 16 * s.n * s.n
-    return {"workload": "gradient: object 512x512, 1024 frames 128x128", "frames_per_s": round(s.K / (ms / 1e3), 1),
-            "ms_per_call": round(ms, 4), "achieved_alg_GBps": round(alg / (ms / 1e3) / 1e9, 1)}
+    return {"workload": "gradient: object 512x512, 1024 frames 128x128", "ms_per_call": round(ms, 4),
+            **_rate(s.K, ms, alg), "alg_bytes_per_call": alg}
 
 
 def probe_form(iters: int = 20) -> dict:
-    """Probe refinement every iteration on the probe-retrieval workload (512^2
-    object, 841 frames of 64^2, Poisson 1e6 photons/frame, probe from the
-    data): ms per iteration without constraints and with the Fourier mask plus
-    the centre-of-mass correction of the probe update."""
+    """Probe refinement every iteration on the probe-retrieval geometry
+    (noiseless, probe from the data): ms per iteration without constraints
+    and with the Fourier mask plus the centre-of-mass correction of the probe
+    update."""
     import numpy as np
     import torch
 
@@ -158,7 +251,7 @@ def probe_form(iters: int = 20) -> dict:
         if center:
             plan.set_probe_constraint(mask=mask)
         plan.set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev)).raar(2, s.beta)
-        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0, t1 = _events()
         torch.cuda.synchronize(dev)
         t0.record()
         plan.raar(iters, s.beta)
@@ -169,32 +262,32 @@ def probe_form(iters: int = 20) -> dict:
     return out
 
 
-def batched_form(iters: int = 20) -> dict:
-    """32 independent uneven scans (n 256..1024, m in {64,128,256}, 100..1500
-    frames), 20 RAAR iterations: batched (one graph launch) vs the same plans
-    iterated one after another."""
+def _batch_compare(scans, iters: int, tuned: bool) -> dict:
+    """Batched (one graph launch per call) vs the same plans iterated one after
+    another, `iters` RAAR iterations of every scan."""
     import numpy as np
     import torch
 
     from paper_1602_01448_amd import Batch, Plan
-    from sharp_data import gen
+    from paper_1602_01448_amd.autotune import batch_options
 
     dev = torch.device("cuda", 0)
-    scans = gen.batch_scans()
+    opts = batch_options(scans) if tuned else [{} for _ in scans]
     plans = []
-    for s in scans:
-        p = Plan(s.n, s.n, s.m, s.positions, device=dev)
+    for s, o in zip(scans, opts):
+        p = Plan(s.n, s.n, s.m, s.positions, device=dev, **o)
         w = torch.from_numpy(s.probe.astype(np.complex64)).to(dev)
         I = p.simulate(torch.from_numpy(s.obj.astype(np.complex64)).to(dev), w)
         p.set_data(I).set_probe(w).set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev))
         plans.append(p)
     frames = sum(s.K for s in scans)
+    B = sum(algorithmic_bytes(s.K, s.m, s.n)["iteration"] for s in scans) * iters
     b = Batch(plans)
     b.raar(iters, 0.75)          # warm-up and graph capture
     for p in plans:
         p.raar(1, 0.75)
     torch.cuda.synchronize(dev)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0, t1 = _events()
     t0.record()
     b.raar(iters, 0.75)
     t1.record()
@@ -206,38 +299,100 @@ def batched_form(iters: int = 20) -> dict:
     t1.record()
     torch.cuda.synchronize(dev)
     ms_p = t0.elapsed_time(t1)
-    return {"workload": f"{len(scans)} uneven scans, {frames} frames, {iters} iterations",
-            "batched_frames_per_s": round(frames * iters / (ms_b / 1e3), 1),
-            "plain_sequential_frames_per_s": round(frames * iters / (ms_p / 1e3), 1),
-            "speedup": round(ms_p / ms_b, 3)}
+    rb, rp = _rate(frames * iters, ms_b, B), _rate(frames * iters, ms_p, B)
+    return {"batched_frames_per_s": rb["frames_per_s"], "batched_alg_GBps": rb["achieved_alg_GBps"],
+            "batched_alg_frac_of_hbm_peak": rb["alg_frac_of_hbm_peak"],
+            "plain_sequential_frames_per_s": rp["frames_per_s"], "plain_sequential_alg_GBps": rp["achieved_alg_GBps"],
+            "speedup": round(ms_p / ms_b, 3), "tuned": bool(tuned and any(opts))}
 
 
-# HBM bytes per iteration of the large-frame kernels from rocprofv3 counters
-# (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the ratios the same counters give
-# for a 1 GiB device copy), summed over the kernel's launches in one
-# iteration, taken on the kernels as they stand; the summary with its
-# commands is profiles/raar_carry_form_2048obj_2025x256_kernels.txt.  To be
-# emptied whenever these kernels change until the counters are taken again.
-MEASURED_TRAFFIC = {("cols", 2): 4_778_800_000, ("merge", 2): 2_218_700_000}
+def batched_form(iters: int = 20) -> dict:
+    """32 independent uneven scans (n 256..1024, m in {64,128,256}, 100..1500
+    frames), 20 RAAR iterations, with the launch options the autotuner stored
+    for the batch."""
+    from sharp_data import gen
+
+    scans = gen.batch_scans()
+    return {"workload": f"{len(scans)} uneven scans, {sum(s.K for s in scans)} frames, {iters} iterations",
+            **_batch_compare(scans, iters, tuned=True)}
 
 
-def traffic_for(kernel: str, form: int, launches_per_iteration: float):
-    v = MEASURED_TRAFFIC.get((kernel, form))
-    return None if v is None else round(v / launches_per_iteration)
+def batched_small_form(iters: int = 20) -> dict:
+    """Many small scans, where batching should pay: 64 independent scans of
+    the small plain shape (object 128^2, 169 frames of 32^2), 20 iterations."""
+    from sharp_data import gen
+
+    scans = gen.small_batch_scans(64)
+    return {"workload": f"{len(scans)} scans of object 128x128, 169 frames 32x32, {iters} iterations",
+            **_batch_compare(scans, iters, tuned=False)}
 
 
-def copy_calibration(nbytes: int = 1 << 30) -> None:
-    """A plain device copy of known size, so that the memory counters of the
-    profiled kernels can be scaled (run under rocprofv3 --pmc)."""
+def library_sha256() -> str:
+    import hashlib
+
+    from paper_1602_01448_amd import _lib
+    h = hashlib.sha256()
+    with open(_lib.LIB_PATH, "rb") as f:
+        for chunk in iter(lambda: f.read(1 << 20), b""):
+            h.update(chunk)
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of `kernel` from the rocprofv3 counter summaries
+    under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by what the same
+    counter reads for a plain device copy).  A summary states its figure on a
+    line 'bench-traffic: kernel=<name> bytes_per_dispatch=<B>
+    libsharp_sha256=<hex>'; the figure is used only when the library loaded
+    now is the one the counters were taken on, else None."""
+    import glob
+
+    want = library_sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("bench-traffic:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if kv.get("kernel") == kernel and kv.get("libsharp_sha256") == want:
+                    return int(kv["bytes_per_dispatch"])
+    return None
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """Plain device-memory references of known size, timed with HIP events
+    (best of `reps`): a copy (nbytes read, nbytes written), a fill (nbytes
+    written) and a sum (nbytes read), all torch's own kernels.  The copy is
+    also what the rocprofv3 memory counters are scaled by: run under
+    rocprofv3 --pmc, its FETCH_SIZE and WRITE_SIZE should read nbytes each."""
     import torch
 
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     a.fill_(1.0)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
-    b.copy_(a)
-    torch.cuda.synchronize()
+
+    def best(fn):
+        t = float("inf")
+        for _ in range(reps):
+            t0, t1 = _events()
+            t0.record()
+            fn()
+            t1.record()
+            torch.cuda.synchronize()
+            t = min(t, t0.elapsed_time(t1))
+        return t
+
+    out = {"bytes": nbytes}
+    for name, fn, moved in (("copy", lambda: b.copy_(a), 2 * nbytes), ("fill", lambda: b.fill_(2.0), nbytes),
+                            ("sum", lambda: a.sum(), nbytes)):
+        ms = best(fn)
+        out[f"{name}_ms"] = round(ms, 4)
+        out[f"{name}_GBps"] = round(moved / (ms / 1e3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
     print(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
+    return out
 
 
 def fig3_form(max_iters: int = 1000, check_every: int = 5, target: float = 5e-4) -> dict:
@@ -286,28 +441,60 @@ def fig3_form(max_iters: int = 1000, check_every: int = 5, target: float = 5e-4)
             "paper": "< 2 s to eps0 < 5e-4 on 16 GTX Titan GPUs in 4 nodes (context, other hardware)"}
 
 
-def cpu_baseline(budget_rows: int = 5, iters: int = 2) -> dict:
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(budget_rows: int = 9, iters: int = 3) -> dict:
     """The FP64 oracle on the frames of the first raster rows of the same
-    scan (an object strip that holds them), timed over `iters` iterations."""
+    scan (an object strip that holds them), timed over `iters` iterations
+    including its set-up, on the host: as it stands with one thread (NumPy's
+    FFT and elementwise work are single-threaded and the path calls no BLAS),
+    and, as a faster CPU variant, the same oracle with its two transforms
+    taken by scipy.fft on every host core."""
     import numpy as np
+    import scipy.fft as sfft
+    from threadpoolctl import threadpool_limits
 
     import oracle as O
     from sharp_data import gen
-
-    from threadpoolctl import threadpool_limits
 
     s = gen.config_scan(3)
     sel = np.where(s.positions[:, 0] < budget_rows * 40 - 2)[0]
     pos = s.positions[sel]
     ny = int(pos[:, 0].max()) + s.m
-    with threadpool_limits(limits=1):          # NumPy's FFT is single-threaded; keep BLAS there too
-        I = O.forward_intensity(s.obj[:ny], s.probe, pos)
+    host_cores = len(os.sched_getaffinity(0))
+    I = O.forward_intensity(s.obj[:ny], s.probe, pos)
+
+    def run():
         t = time.perf_counter()
         O.raar(I, pos, (ny, s.n), s.m, iters, s.beta, psi0=s.psi0[:ny], w0=s.probe)
-        dt = time.perf_counter() - t
-    return {"value": round(len(sel) * iters / dt, 3), "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(sel)} frames of 256x256 (first {budget_rows} raster rows, {ny}x{s.n} object strip), "
-                      f"{iters} RAAR iterations incl. set-up, NumPy FP64, one thread"}
+        return time.perf_counter() - t
+
+    with threadpool_limits(limits=1):
+        dt1 = run()
+    dft, idft = O.dft, O.idft
+    try:   # same sums, taken by scipy's FFT with one worker per host core
+        O.dft = lambda z: sfft.ifft2(np.asarray(z, dtype=np.complex128), norm="ortho", workers=host_cores)
+        O.idft = lambda Z: sfft.fft2(np.asarray(Z, dtype=np.complex128), norm="ortho", workers=host_cores)
+        dtn = run()
+    finally:
+        O.dft, O.idft = dft, idft
+    frames = len(sel) * iters
+    sample = (f"{len(sel)} frames of 256x256 (first {budget_rows} raster rows of the large-frame scan, "
+              f"{ny}x{s.n} object strip), {iters} RAAR iterations incl. set-up, FP64")
+    return {"value": round(frames / dt1, 3), "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": sample + ", NumPy, one thread", "cpu_model": _cpu_model(), "host_cores": host_cores,
+            "variants": [{"kind": "oracle, F and F* by scipy.fft on every host core", "value": round(frames / dtn, 3),
+                          "unit": "frames/s", "cores": host_cores}]}
 
 
 def main() -> int:
@@ -318,8 +505,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not bracket kernels with HIP events")
     ap.add_argument("--no-forms", action="store_true", help="skip the gradient and batched comparisons")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device copy (reference for memory counters)")
+    ap.add_argument("--no-copy-calibration", dest="copy_calibration", action="store_false",
+                    help="skip the 1 GiB device copy / fill / sum references (the copy also scales memory counters)")
     ap.add_argument("--fft-block", type=int, default=0, choices=(0, 128, 256, 512),
                     help="m=256 pass workgroup threads (0: tuned or library default)")
     args = ap.parse_args()
@@ -330,8 +517,7 @@ def main() -> int:
 
     import torch
 
-    if args.copy_calibration:
-        copy_calibration()
+    calib = copy_calibration() if args.copy_calibration else None
     s, plan, ms, kt, eps = gpu_workload(args.steps, args.warmup, not args.no_timing, args.fft_block)
     plan.sync()
     ms_step = ms / args.steps
@@ -361,9 +547,13 @@ def main() -> int:
         "alg_frac_of_hbm_peak": round(B["iteration"] / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
         "eps_a_last": float(eps[-1]) if len(eps) else None,
     }
+    if calib:
+        out["device_memory_reference"] = calib
     if kt:
+        region = kt.pop("region_ms")
         per = {k: {"ms_mean": round(v[0] / v[1], 4), "launches": v[1]} for k, v in kt.items()}
         out["kernels"] = per
+        out["ms_per_step_with_kernel_events"] = round(region / args.steps, 4)
         # dominant kernel: the longest mean launch among those with algorithmic bytes
         dom = max((k for k in per if k in B), key=lambda k: per[k]["ms_mean"])
         # bytes per launch (a kernel may be launched more than once per step)
@@ -371,13 +561,19 @@ def main() -> int:
         per_launch = B[dom] / lpi
         ach = per_launch / (per[dom]["ms_mean"] / 1e3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom, form, lpi),
+                           "frac": round(ach / HBM_PEAK_GBPS, 4),
+                           "traffic": measured_traffic(kernel_names(s.m, form).get(dom, dom)),
                            "kernel": kernel_names(s.m, form).get(dom, dom), "alg_bytes_per_launch": round(per_launch),
                            "launch_ms": per[dom]["ms_mean"]}
     del plan
     if not args.no_forms:
-        out["forms"] = {"grad": grad_form(), "batched": batched_form(), "paper_fig3": fig3_form(),
-                        "probe_constraints": probe_form()}
+        out["forms"] = {}
+        for name, fn in (("plain_small", plain_small_form), ("probe_refinement", probe_refinement_form),
+                         ("grad", grad_form), ("batched", batched_form), ("batched_small", batched_small_form),
+                         ("paper_fig3", fig3_form), ("probe_constraints", probe_form)):
+            print(f"bench: form {name}", file=sys.stderr, flush=True)
+            out["forms"][name] = fn()
+            torch.cuda.empty_cache()
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

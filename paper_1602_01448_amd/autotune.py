@@ -10,7 +10,11 @@ fastest per geometry:
   threads, i.e. 8, 16 or 32 rows / columns of a frame per workgroup);
 * merge tile side (16, 32, 64) and frame-chunk split of the overlap merge,
   for every form that uses the tile merge;
-* the workgroup count of the gradient frame kernel.
+* the workgroup count of the gradient frame kernel;
+* for a batch of scans, one set of per-scan options for the whole batch:
+  library defaults, each scan's own tuned options, or one merge tile side
+  for every scan (the batched launches group scans by frame size and tile
+  side, so uniform choices mean fewer, fuller launches) -- timed as a whole.
 
 Candidates are timed with HIP events over a few RAAR iterations (or gradient
 calls) on synthetic data of the geometry's shape; every candidate computes
@@ -189,6 +193,68 @@ def tune_grad(nx: int, ny: int, m: int, positions, periodic: bool = False, reps:
     return best
 
 
+def batch_key(scans) -> str:
+    h = hashlib.sha1()
+    for sc in scans:
+        h.update(np.asarray([sc.n, sc.n, sc.m], np.int64).tobytes())
+        h.update(np.ascontiguousarray(sc.positions, dtype=np.int32).tobytes())
+    return f"{_arch()}:batch:{len(scans)}:{h.hexdigest()[:12]}"
+
+
+def batch_options(scans, path: str = CACHE) -> list:
+    """Per-scan options the batch tuner stored for this list of scans (each
+    scan: object n x n, frame m, positions), else library defaults."""
+    got = load_cache(path).get(batch_key(scans), {}).get("options")
+    if got is None or len(got) != len(scans):
+        return [{} for _ in scans]
+    return [dict(o) for o in got]
+
+
+def _time_batch(scans, opts, iters: int, reps: int) -> float:
+    from .batch import Batch
+    plans = []
+    for sc, o in zip(scans, opts):
+        p = Plan(sc.n, sc.n, sc.m, sc.positions, **o)
+        obj, probe = _synthetic(p, 1604)
+        p.set_data(p.simulate(obj, probe)).set_probe(probe).set_object(torch.ones_like(obj))
+        plans.append(p)
+    b = Batch(plans)
+    b.raar(iters, 0.75)          # graph capture
+    best = float("inf")
+    for _ in range(reps):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        b.raar(iters, 0.75)
+        t1.record()
+        torch.cuda.synchronize()
+        best = min(best, t0.elapsed_time(t1) / iters)
+    del b, plans
+    return best
+
+
+def tune_batch(scans, iters: int = 3, reps: int = 3, path: str = CACHE, verbose: bool = False) -> list:
+    """Fastest per-scan option set for batched RAAR over `scans`, timed as a
+    whole batch; cached under the batch's geometry key."""
+    cands = {"defaults": [{} for _ in scans],
+             "per_scan_tuned": [lookup("raar", sc.n, sc.n, sc.m, sc.positions, False, path) for sc in scans]}
+    for tile in (16, 32):
+        cands[f"tile{tile}"] = [{} if (sc.m == 256) else {"tile": tile} for sc in scans]
+    best, best_t, tried = None, float("inf"), {}
+    for name, opts in cands.items():
+        t = _time_batch(scans, opts, iters, reps)
+        tried[name] = round(t, 5)
+        if verbose:
+            print(f"  {name}: {t:.4f} ms/iteration", flush=True)
+        if t < best_t:
+            best, best_t = (name, opts), t
+    cache = load_cache(path)
+    cache[batch_key(scans)] = {"options": best[1], "choice": best[0], "ms_per_iteration": round(best_t, 5),
+                               "tried": tried, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    save_cache(cache, path)
+    return best[1]
+
+
 def main() -> None:
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -200,9 +266,12 @@ def main() -> None:
     args = ap.parse_args()
     for w in args.workloads.split(","):
         if w == "batch":
-            for s in gen.batch_scans():
+            scans = gen.batch_scans()
+            for s in scans:
                 print(f"tuning raar {s.name}", flush=True)
                 tune_raar(s.n, s.n, s.m, s.positions, path=args.path, reps=2, iters=2)
+            print("tuning the batch as a whole", flush=True)
+            tune_batch(scans, path=args.path, verbose=True)
             continue
         if w == "fig3":
             s = gen.fig3_scan()

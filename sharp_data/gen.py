@@ -239,3 +239,18 @@ def batch_scans(count: int = 32, n_range=(256, 1024), m_choices=(64, 128, 256),
         scans.append(Scan(f"batch{j:02d}-{n}-{m}x{K}", n, m, pos, obj, probe,
                           _start_object(st["init"], n), None, 0.75, 20, 0, 1, False, st))
     return scans
+
+
+def small_batch_scans(count: int = 64) -> list:
+    """Many small independent scans for the batched form: each has the shape
+    of workload 1 (object 128 x 128, 169 frames of 32 x 32 on a 13 x 13
+    raster with step 8, Gaussian probe sigma 6, noiseless, start U[0,1)).
+    Scan j uses SeedSequence([16027, j])."""
+    scans = []
+    for j in range(count):
+        st = streams_for(np.random.SeedSequence([16027, j]))
+        n, m = 128, 32
+        scans.append(Scan(f"small{j:02d}-128-32x169", n, m, raster_positions(13, 8, n, m),
+                          random_object(st["object"], n, n), gaussian_probe(m, 6.0), _start_object(st["init"], n),
+                          None, 0.75, 20, 0, 1, False, st))
+    return scans
