@@ -50,7 +50,9 @@ enum sharp_status {
     SHARP_ERR_WORKSPACE_TOO_SMALL = -5,
     SHARP_ERR_NONFINITE = -6,             /* NaN/Inf seen in data or in an iterate */
     SHARP_ERR_HIP = -7,                   /* a HIP runtime call failed */
-    SHARP_ERR_HOST_ALLOC = -8             /* host metadata allocation failed */
+    SHARP_ERR_HOST_ALLOC = -8,            /* host metadata allocation failed */
+    SHARP_ERR_SCRATCH_LIMIT = -9          /* sharp_apply_noalloc: the operator needs more scratch
+                                             than SHARP_NOALLOC_SCRATCH_BYTES */
 };
 
 /* Static text for a status code (never NULL). */
@@ -199,6 +201,25 @@ enum sharp_op {
     SHARP_OP_PA = 4, SHARP_OP_PQ = 5, SHARP_OP_OBJECT = 6
 };
 int sharp_apply(sharp_plan plan, int op, const void* d_in, void* d_out);
+
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * operators as sharp_apply, same arguments and results, with their scratch
+ * taken from a fixed array of SHARP_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each device it runs on (from the first call on that device until
+ * the process ends) instead of from the plan's workspace.  The scratch is
+ * the m = 256 stage buffer of F, F* and P_a (K m^2 complex64), the residual
+ * partials of P_a, the object temporary of P_Q (ny nx complex64) and the
+ * frame-chunk partials of a split merge.  Allocates and frees nothing.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (several streams or host threads) race.  Must be called with
+ * the plan's device current.
+ * Errors: as sharp_apply, and SCRATCH_LIMIT (checked first, before any
+ * device work) when the operator needs more scratch than the array holds.
+ * ---------------------------------------------------------------------- */
+#define SHARP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int sharp_apply_noalloc(sharp_plan plan, int op, const void* d_in, void* d_out);
 
 /* ------------------------------------------------------------------------
  * Checkpoint / resume of the iteration state (carry frames, object terms,

@@ -19,7 +19,7 @@ STATUS = {
     0: "SHARP_OK", -1: "SHARP_ERR_INVALID_ARG", -2: "SHARP_ERR_UNSUPPORTED_SIZE",
     -3: "SHARP_ERR_POSITION_OUT_OF_RANGE", -4: "SHARP_ERR_NOT_READY",
     -5: "SHARP_ERR_WORKSPACE_TOO_SMALL", -6: "SHARP_ERR_NONFINITE", -7: "SHARP_ERR_HIP",
-    -8: "SHARP_ERR_HOST_ALLOC",
+    -8: "SHARP_ERR_HOST_ALLOC", -9: "SHARP_ERR_SCRATCH_LIMIT",
 }
 OPS = {"F": 0, "FINV": 1, "Q": 2, "QSTAR": 3, "PA": 4, "PQ": 5, "OBJECT": 6}
 
@@ -69,6 +69,7 @@ SIGNATURES = [
     ("sharp_grad", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("sharp_simulate", c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("sharp_apply", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    ("sharp_apply_noalloc", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     ("sharp_state_bytes", c_size_t, [c_void_p]),
     ("sharp_get_state", c_int, [c_void_p, c_void_p]),
     ("sharp_set_state", c_int, [c_void_p, c_void_p]),

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsharp.so")
-SOURCES = ["kernels_frame.hip", "kernels_merge.hip", "sharp_api.cpp", "sharp_batch.cpp"]
+SOURCES = ["kernels_frame.hip", "kernels_merge.hip", "sharp_api.cpp", "sharp_batch.cpp", "sharp_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

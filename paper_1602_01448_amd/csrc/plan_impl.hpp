@@ -87,6 +87,16 @@ namespace sharp {
 // argument blocks of a plan's kernels (sharp_api.cpp)
 FrameArgs frame_args(const sharp_plan_s& p);
 MergeArgs merge_args(const sharp_plan_s& p);
+// sharp_apply with its scratch segments taken from `scratch` (device memory of
+// at least apply_scratch(p, op).total bytes, 256-byte aligned) instead of the
+// workspace when it is not null
+struct ApplyScratch {
+    size_t stage, resid, tmp_obj, mpart, total;
+};
+ApplyScratch apply_scratch(const sharp_plan_s& p, int op);
+// host-side argument and readiness checks of sharp_apply (no device work)
+int apply_check(const sharp_plan_s& p, int op, const void* d_in, const void* d_out);
+int apply_into(sharp_plan_s& p, int op, const void* d_in, void* d_out, char* scratch);
 // number of per-block residual partials an iteration's frame launch writes
 int resid_blocks(const sharp_plan_s& p);
 // the same for the default launch shape (used by batched execution)

@@ -51,6 +51,9 @@ extern "C" const char* sharp_status_string(int s) {
         case SHARP_ERR_NONFINITE: return "non-finite value in data or iterate";
         case SHARP_ERR_HIP: return "HIP runtime error";
         case SHARP_ERR_HOST_ALLOC: return "host allocation failed";
+        case SHARP_ERR_SCRATCH_LIMIT:
+            return "the operator needs more scratch than the allocation-free entry point holds "
+                   "(SHARP_NOALLOC_SCRATCH_BYTES)";
     }
     return "unknown status";
 }
@@ -706,15 +709,53 @@ extern "C" int sharp_simulate(sharp_plan p, const void* d_psi, const void* d_w, 
     return SHARP_OK;
 }
 
-extern "C" int sharp_apply(sharp_plan p, int op, const void* d_in, void* d_out) {
-    if (!p || !d_in || !d_out || d_in == d_out) return SHARP_ERR_INVALID_ARG;
+// Scratch the operators of sharp_apply use beyond their input and output:
+// the row-transformed frames between the passes of the m = 256 frame kernels,
+// the residual partials the data projector writes, the object temporary of
+// P_Q and the frame-chunk partials of a split merge.  Offsets into one buffer.
+ApplyScratch sharp::apply_scratch(const sharp_plan_s& p, int op) {
+    ApplyScratch S{};
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = cur;
+        cur = align_up(cur + bytes);
+        return at;
+    };
+    const bool frame_op = op == SHARP_OP_F || op == SHARP_OP_FINV || op == SHARP_OP_PA;
+    const bool merge_op = op == SHARP_OP_QSTAR || op == SHARP_OP_OBJECT || op == SHARP_OP_PQ;
+    S.stage = take(frame_op && p.m == 256 ? p.frame_elems() * sizeof(float2) : 0);
+    S.resid = take(op == SHARP_OP_PA ? p.resid_cap * sizeof(float) : 0);
+    S.tmp_obj = take(op == SHARP_OP_PQ ? p.obj_elems() * sizeof(float2) : 0);
+    S.mpart = take(merge_op && p.split > 1 ? (size_t)p.ntiles * p.split * p.T * p.T * 2 * sizeof(float4) : 0);
+    S.total = cur;
+    return S;
+}
+
+int sharp::apply_check(const sharp_plan_s& p, int op, const void* d_in, const void* d_out) {
+    if (op < SHARP_OP_F || op > SHARP_OP_OBJECT || !d_in || !d_out || d_in == d_out) return SHARP_ERR_INVALID_ARG;
+    if (!p.has_ws) return SHARP_ERR_NOT_READY;
+    if (op != SHARP_OP_F && op != SHARP_OP_FINV && !p.has_probe) return SHARP_ERR_NOT_READY;
+    if (op == SHARP_OP_PA && !p.has_data) return SHARP_ERR_NOT_READY;
+    return SHARP_OK;
+}
+
+int sharp::apply_into(sharp_plan_s& pl, int op, const void* d_in, void* d_out, char* scratch) {
+    sharp_plan_s* p = &pl;
+    if (!d_in || !d_out || d_in == d_out) return SHARP_ERR_INVALID_ARG;
     p->stage_gather = false;  // the stage buffer is about to be reused or the gather is out of date
-    if (!p->has_ws) return SHARP_ERR_NOT_READY;
-    if (op != SHARP_OP_F && op != SHARP_OP_FINV && !p->has_probe) return SHARP_ERR_NOT_READY;
-    if (op == SHARP_OP_PA && !p->has_data) return SHARP_ERR_NOT_READY;
+    const int chk = apply_check(*p, op, d_in, d_out);
+    if (chk != SHARP_OK) return chk;
     hipStream_t s = p->stream;
     FrameArgs A = frame_args(*p);
     MergeArgs Mg = merge_args(*p);
+    float2* tmp_obj = p->at<float2>(p->off.tmp_obj);
+    if (scratch) {  // the caller's scratch replaces the workspace segments the operators use as scratch
+        const ApplyScratch S = apply_scratch(*p, op);
+        if (p->m == 256) A.stage = reinterpret_cast<float2*>(scratch + S.stage);
+        A.resid = reinterpret_cast<float*>(scratch + S.resid);
+        tmp_obj = reinterpret_cast<float2*>(scratch + S.tmp_obj);
+        Mg.part = reinterpret_cast<float4*>(scratch + S.mpart);
+    }
     switch (op) {
         case SHARP_OP_F:
         case SHARP_OP_FINV:
@@ -736,14 +777,19 @@ extern "C" int sharp_apply(sharp_plan p, int op, const void* d_in, void* d_out) 
             return SHARP_OK;
         case SHARP_OP_PQ:
             Mg.u = (const float2*)d_in;
-            Mg.out = p->at<float2>(p->off.tmp_obj);
+            Mg.out = tmp_obj;
             HIPCHK(launch_merge(MK_OBJ, Mg, p->ntiles, s));
-            A.psi = p->at<float2>(p->off.tmp_obj);
+            A.psi = tmp_obj;
             A.out = (float2*)d_out;
             HIPCHK(launch_frame(FM_Q, A, 0, s, nullptr));
             return SHARP_OK;
     }
     return SHARP_ERR_INVALID_ARG;
+}
+
+extern "C" int sharp_apply(sharp_plan p, int op, const void* d_in, void* d_out) {
+    if (!p) return SHARP_ERR_INVALID_ARG;
+    return apply_into(*p, op, d_in, d_out, nullptr);
 }
 
 // ---------------------------------------------------------------------------

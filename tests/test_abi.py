@@ -51,10 +51,10 @@ def _create(L, n, m, pos, **kw):
 
 
 def test_status_strings(L):
-    for s in range(-8, 1):
-        assert len(L.sharp_status_string(s)) > 0
+    for s in range(-9, 1):
+        assert len(L.sharp_status_string(s)) > 0 and L.sharp_status_string(s) != b"unknown status"
     assert L.sharp_status_string(-99) == b"unknown status"
-    assert L.sharp_status_string(-9) == b"unknown status"
+    assert L.sharp_status_string(-10) == b"unknown status"
 
 
 @pytest.mark.parametrize("m,expect", [(16, 0), (32, 0), (64, 0), (128, 0), (256, 0), (48, -2), (8, -2), (512, -2)])
@@ -209,3 +209,22 @@ def test_workspace_grows_with_frames(L):
         assert sizes[-1] % 256 == 0
         L.sharp_plan_destroy(h)
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+def test_noalloc_scratch_limit_checked_before_device_work(L):
+    """sharp_apply_noalloc refuses an operator whose scratch exceeds its fixed
+    array (64 MiB): 200 frames of 256^2 need a 100 MiB stage buffer for F.
+    The check comes before any device call (no workspace is set here); an
+    operator that fits gets the plan's usual NOT_READY instead."""
+    pos = [(0, 0)] * 200
+    st, h = _create(L, 256, 256, pos)
+    assert st == 0
+    dummy = ctypes.c_void_p(256)
+    assert L.sharp_apply_noalloc(h, 0, dummy, ctypes.c_void_p(512)) == -9    # F: stage 200 x 512 KiB
+    assert L.sharp_apply_noalloc(h, 4, dummy, ctypes.c_void_p(512)) == -9    # P_a likewise
+    assert L.sharp_apply_noalloc(h, 7, dummy, ctypes.c_void_p(512)) == -1    # no such operator
+    assert L.sharp_apply_noalloc(None, 0, dummy, ctypes.c_void_p(512)) == -1
+    L.sharp_plan_destroy(h)
+    st, h = _create(L, 64, 32, [(0, 0), (8, 8)])
+    assert L.sharp_apply_noalloc(h, 5, dummy, ctypes.c_void_p(512)) == -4    # fits; no workspace yet
+    L.sharp_plan_destroy(h)
