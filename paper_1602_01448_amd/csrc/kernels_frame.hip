@@ -235,6 +235,20 @@ struct ModOp {
         const float2 p = cscale(s, av);
         return (MODE == FM_GRAD) ? csub(v, p) : p;
     }
+    // The same with selects instead of a branch on |v| > 0 (identical results;
+    // fewer instructions where the branch would be taken per element, more
+    // registers live, so only the kernels with registers to spare use it).
+    __device__ __forceinline__ float2 modulus_sel(float2 v, float av) {
+        const float n2 = cabs2(v);
+        const bool nz = n2 > 0.f;
+        const float r = rsqrtf(nz ? n2 : 1.f);
+        const float2 s = nz ? cscale(v, r) : make_float2(1.f, 0.f);
+        const float mag = nz ? n2 * r : 0.f;
+        const float d = mag - av;
+        resid += d * d;
+        const float2 p = cscale(s, av);
+        return (MODE == FM_GRAD) ? csub(v, p) : p;
+    }
 };
 
 __device__ __forceinline__ float block_sum(float x, float* red) {
@@ -1537,6 +1551,256 @@ __global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// m = 256, form 3: the column pass forms its own row transform.
+//
+// The row transform of the gathered frame g = w_g T psi_v factors with
+// x = 16 n1 + n2 and kx = k1 + 16 k2 as
+//   G[y][k1 + 16 k2] = sum_n2 W16^(k2 n2) W256^(k1 n2) sum_n1 g[y][16 n1 + n2] W16^(k1 n1),
+// so the 64 columns with k1 in {4q, .., 4q + 3} need only the four inner sums
+// k1 = 4q + i of every (y, n2).  One 1024-thread workgroup takes one quarter
+// q of one frame: it gathers the whole frame (the object window and the probe
+// come from the caches), forms those inner sums (four radix-4 DFTs over n1 / 4
+// and a four-term combination), twiddles them, runs the sixteen-point DFTs
+// over n2, and then does what the column pass of the two-pass form does on its
+// 64 columns: column FFTs, Z = U + (g / m) G, eps_a partials, Y = a sgn Z,
+// U' = beta Z + (1 - 2 beta) Y, V = 2Y - Z, inverse column FFTs.  The merge
+// input leaves with each row's 256 values in k1-major order (16 k1 + k2), the
+// order in which the strip pass's line transforms read them.  The four
+// workgroups of a frame each repeat the gather and the n1 sums (the price of
+// dropping the row-transformed frame's trip through memory).
+//
+// LDS: one 128 KiB buffer, laid out three ways in turn (inner sums, columns,
+// rows of the result); the XOR swizzles keep the wavefront access patterns
+// of each phase at two-way bank sharing (the minimum for 64-bit accesses).
+// ---------------------------------------------------------------------------
+// The swizzles follow this GPU's LDS banking, measured with the bank-conflict
+// counter: 64 banks of 4 bytes, and a 64-bit access served per half
+// wavefront (32 lanes), each half taking as many cycles as its most
+// requested bank has distinct words -- so a half wavefront's 32 float2 must
+// fall on 32 distinct slots modulo 32 float2.
+namespace colg {
+constexpr int M = 256, NT = 1024, QE = 64 * M;  // quarter: 64 columns x 256 rows
+// inner sums S'(y, i, n2): written by 8 n2-pairs x 4 rows (y bits 5, 6) per
+// half wavefront, read by 32 consecutive rows
+__device__ __forceinline__ int l1(int y, int i, int n2) {
+    const int f = (y & 31) ^ ((y >> 5) & 1) ^ (((y >> 6) & 1) << 4);
+    return y * 64 + ((i * 16 + n2) ^ f);
+}
+// column c (0..63), position p (0..255) along the column
+__device__ __forceinline__ int l2(int c, int p) { return c * M + (p ^ ((p >> 4) & 15) ^ ((c & 3) << 4)); }
+// result rows: row y, column c; written by 2 columns x 16 rows, read in
+// 16-byte pairs (2 c', 2 c' + 1) of one row (the XOR keeps a pair adjacent,
+// swapped when bit 0 of the mask is set -- it never is: the mask is even)
+__device__ __forceinline__ int l3(int y, int c) { return y * 64 + (c ^ ((y & 15) << 1)); }
+// per-thread twiddles W^(j r) of the column lines: T[j][r] at 17 j + r
+constexpr int TW17 = 16 * 17;
+}  // namespace colg
+
+// 256-point line held as v[r] = element j + 16 r by the 16 threads (j) of a
+// line (one wavefront holds four lines): two radix-16 stages with one
+// exchange through the line's LDS positions; ends with v[q] = element
+// j + 16 q of the transform.  `at(p)` maps a line position to LDS.
+template <int DIR, class At>
+__device__ __forceinline__ void colg_line(float2 (&v)[16], float2* lds, const float2* tw17, int j_in, At at) {
+    // the LDS addresses are formed again in each call instead of being held
+    // live (in registers) from one transform to the next
+    const int j = opaque(j_in) & 15;
+    dft<16, DIR>(v);
+    line_sync();   // every thread of the line has read its inputs
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lds[at(16 * j + q)] = v[q];
+    line_sync();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = lds[at(j + 16 * r)];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) {
+        float2 t = tw17[17 * j + r];
+        if constexpr (DIR < 0) t.y = -t.y;
+        v[r] = cmul(v[r], t);
+    }
+    dft<16, DIR>(v);
+}
+
+// Gather and inner sums of the column pass with its own row transform: for
+// every row y and n2 the four sums S(k1) = sum_n1 g[y][16 n1 + n2] W16^(k1 n1),
+// k1 = 4 quarter + i, times W256^(k1 n2), into LDS.  A thread takes the pair
+// n2 = 2h, 2h + 1 of two rows: 16-byte requests for the object and the probe
+// (the object window starts anywhere, so its pairs are 8-byte aligned).  With
+// n1 = 4a + b the 16 terms of each sum are taken b by b, four requests of
+// each kind in flight per step.
+template <bool PERIODIC>
+__device__ __forceinline__ void colg_inner_sums(const FrameArgs& A, int py, int px, int quarter, float2* lds,
+                                                const float2* twl) {
+    using namespace colg;
+    typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+    const int tid = opaque_tid();
+    const int h = tid & 7, rr = (tid >> 3) & 7, wv = tid >> 6;
+    const int nx = A.nx, ny = A.ny;
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        const int y = (rr << 5) | (opaque(half) << 4) | wv;
+        int gy = py + y;
+        if constexpr (PERIODIC) gy = wrap(gy, ny);
+        const float2* prow = A.psi + (size_t)gy * nx;
+        const float2* wrow = A.w_g + y * M + 2 * h;
+        float2 sacc[2][4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            float2 x[2][4];   // [n2 of the pair][a]
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int n1 = 4 * a + b;
+                const int gx = px + 16 * n1 + 2 * h;
+                float2 p0, p1;
+                if constexpr (!PERIODIC) {
+                    const f4a8 t = *reinterpret_cast<const f4a8*>(prow + gx);
+                    p0 = make_float2(t.x, t.y);
+                    p1 = make_float2(t.z, t.w);
+                } else {
+                    const int g0 = wrap(gx, nx);   // gx < 2 nx
+                    p0 = prow[g0];
+                    p1 = prow[g0 + 1 == nx ? 0 : g0 + 1];
+                }
+                float2 w0, w1;
+                ld2(wrow, 16 * n1, w0, w1);
+                x[0][a] = cmul(w0, p0);
+                x[1][a] = cmul(w1, p1);
+            }
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                // T[b][i] = sum_a x[4a + b] W4^(a i), then the b term of each k1 sum
+                dft4<1>(x[e][0], x[e][1], x[e][2], x[e][3]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float2 term = b == 0 ? x[e][i] : cmul(x[e][i], w16<1>(b * (4 * quarter + i)));
+                    sacc[e][i] = b == 0 ? term : cadd(sacc[e][i], term);
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)   // times W256^(k1 n2)
+                lds[l1(y, i, 2 * h + e)] = cmul(sacc[e][i], twl[((4 * quarter + i) * (2 * h + e)) & 255]);
+    }
+}
+
+template <bool STREAM>
+__device__ float colg_item(const FrameArgs& A, int frame, int quarter, float2* lds, const float2* twl) {
+    using namespace colg;
+    const int tid = opaque_tid();
+    const int py = A.pos[2 * frame], px = A.pos[2 * frame + 1];
+    const int nx = A.nx, ny = A.ny;
+    const unsigned MM = M * M;
+    // ---- gather and the inner sums over n1 for k1 = 4 quarter + i ----------
+    if (A.periodic) colg_inner_sums<true>(A, py, px, quarter, lds, twl);
+    else colg_inner_sums<false>(A, py, px, quarter, lds, twl);
+    __syncthreads();
+    // ---- sixteen-point DFTs over n2: G[y][4 quarter + i + 16 k2] ------------
+    {
+        const int y = tid & 255, i = tid >> 8;
+        float2 v[16];
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) v[n2] = lds[l1(y, i, n2)];
+        __syncthreads();   // the inner sums are read before the columns take the buffer
+        dft<16, 1>(v);
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) lds[l2(i * 16 + k2, y)] = v[k2];
+    }
+    __syncthreads();
+    // ---- columns ------------------------------------------------------------
+    const int col = tid >> 4, j = tid & 15;
+    auto at = [col](int p) { return colg::l2(col, p); };
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = lds[at(j + 16 * r)];
+    // carry and amplitudes of rows j + 16 q of this column (q256 layout: the
+    // pair q, q + 1 of every thread of the column lies side by side, so a
+    // request of the 16 threads covers 256 contiguous bytes); the amplitudes
+    // and the first half of the carry are requested ahead of the forward
+    // column transform, the second half after it
+    const size_t qb = (size_t)frame * MM + (size_t)quarter * QE;
+    const unsigned cofs = (unsigned)col * M + 2u * j;
+    float2 uc[8];
+    float ac[16];
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+        const float2 t = ldf2t<STREAM>(A.at + qb, cofs + 16 * q);
+        ac[q] = t.x;
+        ac[q + 1] = t.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) ld2t<STREAM>(A.u + qb, cofs + 16 * q, uc[q], uc[q + 1]);
+    colg_line<1>(v, lds, twl + 256, j, at);
+    const float gm = A.g * (1.0f / M), b = A.beta, c1 = 1.f - 2.f * A.beta;
+    ModOp<FM_RAAR, M> op{nullptr, nullptr, 0.f};
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        if (half == 1) {
+#pragma unroll
+            for (int q = 0; q < 8; q += 2) ld2t<STREAM>(A.u + qb, cofs + 16 * (8 + q), uc[q], uc[q + 1]);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) {
+            const int e = 8 * half + q;
+            float2 un[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float2 z = cadd(uc[q + h], cscale(v[e + h], gm));
+                const float2 yv = op.modulus_sel(z, ac[e + h]);
+                un[h] = cadd(cscale(z, b), cscale(yv, c1));
+                v[e + h] = csub(cscale(yv, 2.f), z);
+            }
+            st2t<STREAM>(A.u + qb, cofs + 16 * e, un[0], un[1]);
+        }
+    }
+    colg_line<-1>(v, lds, twl + 256, j, at);
+    __syncthreads();   // every column is done with the buffer
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lds[colg::l3(j + 16 * q, col)] = v[q];
+    __syncthreads();
+    // ---- rows of the result: 512 contiguous bytes per row ---------------------
+    {
+        const int c2 = tid & 31;
+        float2* dst = A.stage + (size_t)frame * MM + 64 * quarter + 2 * c2;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int y = (tid >> 5) + 32 * k;
+            const float4 pr = *reinterpret_cast<const float4*>(lds + colg::l3(y, 2 * c2));   // 16-byte read
+            st2t<STREAM>(dst, (unsigned)y * M, make_float2(pr.x, pr.y), make_float2(pr.z, pr.w));
+        }
+    }
+    __syncthreads();
+    return op.resid;
+}
+
+// Workgroup b: XCD b mod 8 takes frames [x F, (x + 1) F) in order (F = ceil(K / 8)),
+// the four quarters of a frame one after another, so that a frame's object
+// window and its neighbours' stay in that XCD's L2 while they are reused.
+template <bool STREAM>
+__global__ void __launch_bounds__(1024) colg_kernel(FrameArgs A) {
+    extern __shared__ float2 smem[];
+    __shared__ float red[16];
+    float2* lds = smem;
+    float2* twl = smem + colg::QE;   // W^t, t < 256, then the padded table T[j][r] = W^(j r) at 256 + 17 j + r
+    for (int t = threadIdx.x; t < 256; t += 1024) twl[t] = A.tw[t];
+    for (int t = threadIdx.x; t < colg::TW17; t += 1024) {
+        const int j = t / 17, r = t % 17;
+        twl[256 + t] = A.tw[(j * r) & 255];
+    }
+    const int fpx = (A.K + 7) >> 3;
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int frame = xcd * fpx + (local >> 2), quarter = local & 3;
+    if (frame >= A.K) return;
+    __syncthreads();
+    const float r = colg_item<STREAM>(A, frame, quarter, lds, twl);
+    const float s = block_sum(r, red);
+    if (threadIdx.x == 0) A.resid[4 * frame + quarter] = s;
+}
+
+size_t colg_smem() { return (size_t)(colg::QE + 256 + colg::TW17) * sizeof(float2); }
+
 // Inverse row FFTs of the frame rows that land in object strip s (SH rows),
 // multiplied by conj(w) and summed in ascending frame order into the strip,
 // then psi_v = D^+ * sum (the 1/m of F* is applied to the sum).  Thread t owns the strip pixels whose column is
@@ -1674,6 +1938,7 @@ __device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b,
     __syncthreads();
 }
 
+template <bool K1M>
 __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int strip, float2* lds, const float2* twl,
                                  float2* acc) {
     constexpr int M = 256, NT = 256, LINES = kStripLines, MM = M * M;
@@ -1690,10 +1955,18 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
     float2 v[16];
     // an absent line (record frame -1, row 0, x 0) reads frame 0 row 0: in
     // bounds, and its transform is never summed
+    // element j + 16 r of a line: natural order (stride 16), or k1-major rows
+    // (16 consecutive values)
     auto load_line = [&](const int4& rec) {
-        const float2* src = A.stage + (size_t)(rec.x < 0 ? 0 : rec.x) * MM + (size_t)rec.y * M + j;
+        if constexpr (K1M) {
+            const float2* src = A.stage + (size_t)(rec.x < 0 ? 0 : rec.x) * MM + (size_t)rec.y * M + 16 * j;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = src[16 * r];
+            for (int r = 0; r < 16; ++r) v[r] = src[r];
+        } else {
+            const float2* src = A.stage + (size_t)(rec.x < 0 ? 0 : rec.x) * MM + (size_t)rec.y * M + j;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = src[16 * r];
+        }
     };
     // records are fetched two batches ahead, so that the lines of the next
     // batch can be requested at once (no wait for a record load in between)
@@ -1780,7 +2053,10 @@ __global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripA
     float2* acc = twl + 256;
     for (int t = threadIdx.x; t < 256; t += 256) twl[t] = A.tw[t];
     __syncthreads();
-    strip_merge_item(A, S, S.strip0 + blockIdx.x, lds, twl, acc);
+    const int slot = S.strip0 + blockIdx.x;
+    const int strip = S.order ? S.order[slot] : slot;
+    if (S.k1major) strip_merge_item<true>(A, S, strip, lds, twl, acc);
+    else strip_merge_item<false>(A, S, strip, lds, twl, acc);
 }
 
 // Batched form: phase 0 gather + row FFTs, 1 column pass with the carry,
@@ -1810,7 +2086,7 @@ __global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(co
         const float s = block_sum(r, red);
         if (threadIdx.x == 0) A.resid[w.y] = s;
     } else {
-        strip_merge_item(A, CH.s[w.x - CH.base], w.y, lds, twl, twl + 256);
+        strip_merge_item<false>(A, CH.s[w.x - CH.base], w.y, lds, twl, twl + 256);
     }
 }
 
@@ -1840,7 +2116,9 @@ hipError_t launch_batch_carry(int phase, const BatchArgs& C, const FrameArgs* D,
 }
 
 // Carry <-> space: u = F* U (column pass then row pass) and U = F u.
-__global__ void __launch_bounds__(256) carry_cols_kernel(FrameArgs A, int dir) {
+// Column transforms of the carry conversions; `layout` is that of the carry
+// (CL_CB256 or CL_Q256).
+__global__ void __launch_bounds__(256) carry_cols_kernel(FrameArgs A, int dir, int layout) {
     using C = MP<256, 256>;
     constexpr int M = 256, NT = C::NT, NP = C::NP, CB = C::CB, MM = M * M, NCB = C::NCB;
     extern __shared__ float2 smem[];
@@ -1857,8 +2135,14 @@ __global__ void __launch_bounds__(256) carry_cols_kernel(FrameArgs A, int dir) {
             const int e0 = 2 * (tid + NT * k);
             const int y = e0 / CB, c = e0 % CB;
             float2 a0, a1;
-            if (dir < 0) ld2(A.in + blk, e0, a0, a1);                    // carry block
-            else ld2(A.stage + fb, y * M + cb * CB + c, a0, a1);         // row-transformed frame
+            if (dir < 0 && layout == CL_Q256) {                           // carry, q256
+                a0 = A.in[fb + q256(y, cb * CB + c)];
+                a1 = A.in[fb + q256(y, cb * CB + c + 1)];
+            } else if (dir < 0) {
+                ld2(A.in + blk, e0, a0, a1);                              // carry block
+            } else {
+                ld2(A.stage + fb, y * M + cb * CB + c, a0, a1);           // row-transformed frame
+            }
             lds[pidx(e0)] = a0;
             lds[pidx(e0 + 1)] = a1;
         }
@@ -1871,8 +2155,14 @@ __global__ void __launch_bounds__(256) carry_cols_kernel(FrameArgs A, int dir) {
             const int e0 = 2 * (tid + NT * k);
             const int y = e0 / CB, c = e0 % CB;
             const float2 v0 = lds[pidx(e0)], v1 = lds[pidx(e0 + 1)];
-            if (dir < 0) st2(A.stage + fb, y * M + cb * CB + c, v0, v1);
-            else st2(A.out + blk, e0, cscale(v0, 1.0f / M), cscale(v1, 1.0f / M));
+            if (dir < 0) {
+                st2(A.stage + fb, y * M + cb * CB + c, v0, v1);
+            } else if (layout == CL_Q256) {
+                A.out[fb + q256(y, cb * CB + c)] = cscale(v0, 1.0f / M);
+                A.out[fb + q256(y, cb * CB + c + 1)] = cscale(v1, 1.0f / M);
+            } else {
+                st2(A.out + blk, e0, cscale(v0, 1.0f / M), cscale(v1, 1.0f / M));
+            }
         }
         __syncthreads();
     }
@@ -1934,6 +2224,27 @@ hipError_t launch_col_carry_256(const FrameArgs& A, hipStream_t s, const Timer* 
     return hipGetLastError();
 }
 
+hipError_t launch_colg_256(const FrameArgs& A, hipStream_t s, const Timer* tp) {
+    const Timer& t = tp ? *tp : kNoTimer;
+    if (A.K <= 0) return hipSuccess;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)colg_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)colg_smem());
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)colg_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)colg_smem());
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int grid = 32 * ((A.K + 7) / 8);
+    t.begin(TC_COLS, s);
+    if (A.stream) hipLaunchKernelGGL(colg_kernel<true>, dim3(grid), dim3(1024), colg_smem(), s, A);
+    else hipLaunchKernelGGL(colg_kernel<false>, dim3(grid), dim3(1024), colg_smem(), s, A);
+    t.end(TC_COLS, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_strip_256(const FrameArgs& A, const StripArgs& S, int s0, int s1, hipStream_t s,
                             const Timer* tp) {
     const Timer& t = tp ? *tp : kNoTimer;
@@ -1954,18 +2265,18 @@ hipError_t launch_strip_256(const FrameArgs& A, const StripArgs& S, int s0, int 
 }
 
 // u = F* U for the K frames of A.in (carry blocks) into A.out (natural layout)
-hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s) {
+hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s, int layout) {
     using C = MP<256, 256>;
-    hipLaunchKernelGGL(carry_cols_kernel, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A, -1);
+    hipLaunchKernelGGL(carry_cols_kernel, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A, -1, layout);
     hipLaunchKernelGGL(carry_rows_inv_kernel, dim3(A.K * C::NRB), dim3(256), C::SMEM, s, A);
     return hipGetLastError();
 }
 
 // U = F u for the K frames of A.in (natural layout) into A.out (carry blocks)
-hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s) {
+hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s, int layout) {
     using C = MP<256, 256>;
     hipLaunchKernelGGL((mp_row_fwd<256, FM_F, 256>), dim3(A.K * C::NRB), dim3(256), C::SMEM, s, A);
-    hipLaunchKernelGGL(carry_cols_kernel, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A, 1);
+    hipLaunchKernelGGL(carry_cols_kernel, dim3(A.K * C::NCB), dim3(256), C::SMEM, s, A, 1, layout);
     return hipGetLastError();
 }
 

@@ -220,7 +220,7 @@ __device__ __forceinline__ float block_sum256(float x, float* red) {
 
 __global__ void __launch_bounds__(256) set_data_kernel(const float* __restrict__ I, float* __restrict__ a, size_t n,
                                                        float* __restrict__ partials, int* __restrict__ flag,
-                                                       int blocked256, float* __restrict__ a_t128) {
+                                                       int blocked256, float* __restrict__ a2, int a2_q256) {
     __shared__ float red[4];
     float s = 0.f;
     bool bad = false;
@@ -234,9 +234,14 @@ __global__ void __launch_bounds__(256) set_data_kernel(const float* __restrict__
             o = (i - p) + cb256(p >> 8, p & 255u);
         }
         a[o] = r;
-        if (a_t128) {  // second copy, each 128 x 128 frame transposed
-            const unsigned p = (unsigned)(i & 16383u);
-            a_t128[(i - p) + (p & 127u) * 128u + (p >> 7)] = r;
+        if (a2) {
+            if (a2_q256) {  // second copy of a 256 x 256 frame in the q256 layout
+                const unsigned p = (unsigned)(i & 65535u);
+                a2[(i - p) + q256(p >> 8, p & 255u)] = r;
+            } else {        // second copy, each 128 x 128 frame transposed
+                const unsigned p = (unsigned)(i & 16383u);
+                a2[(i - p) + (p & 127u) * 128u + (p >> 7)] = r;
+            }
         }
         s += r * r;
     }
@@ -341,9 +346,10 @@ __global__ void __launch_bounds__(256) fill_kernel(uint4* __restrict__ p, size_t
 }
 
 hipError_t launch_set_data(const float* I, float* a, size_t n, float* partials, int* flag, hipStream_t s,
-                           int* blocks_used, int blocked256, float* a_t128) {
+                           int* blocks_used, int blocked256, float* a2, int a2_q256) {
     const int grid = (int)std::min<size_t>(std::max<size_t>((n + 255) / 256, 1), 2048);
-    hipLaunchKernelGGL(set_data_kernel, dim3(grid), dim3(256), 0, s, I, a, n, partials, flag, blocked256, a_t128);
+    hipLaunchKernelGGL(set_data_kernel, dim3(grid), dim3(256), 0, s, I, a, n, partials, flag, blocked256, a2,
+                       a2_q256);
     *blocks_used = grid;
     return hipGetLastError();
 }

@@ -22,7 +22,7 @@ inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
 
 struct Offsets {
     size_t tw, pos, tile_ptr, tile_frames, a, a_t, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
-    size_t w_cur, w_gat, tmp_w, tmp_w2, pcons, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sln, total;
+    size_t w_cur, w_gat, tmp_w, tmp_w2, pcons, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sln, sord, total;
 };
 
 }  // namespace sharp
@@ -33,9 +33,11 @@ struct sharp_plan_s {
     std::vector<int32_t> pos;
     int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0, split = 1, grad_groups = 0, probe_chunks = 1;
     int frame_launch = 1;     // 1 = carry in frame space; 2 = carry in the Fourier domain (m = 128: one
-                              // frame kernel + tile merge; m = 256: column pass + strip pass)
+                              // frame kernel + tile merge; m = 256: column pass + strip pass); 3 (m = 256):
+                              // Fourier carry, column pass forming its own row transform + strip pass
     int SH = 0, nstrips = 0;  // strip merge: object rows per strip (0 = form unavailable)
     std::vector<int32_t> strip_ptr, strip_lines;  // strip_lines: 4 ints per (entry, strip row)
+    std::vector<int32_t> strip_order;             // strips by descending frame-row count (launch order)
     int fft_block = 256;      // m = 256, three launches: threads per pass workgroup
     std::vector<int32_t> tile_ptr, tile_frames;
     sharp::Offsets off{};
@@ -70,8 +72,10 @@ struct sharp_plan_s {
     const sharp::Timer* tm() const { return timing ? &timer : nullptr; }
 
     template <class T> T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
-    bool carry_form() const { return (m == 128 || m == 256) && frame_launch == 2; }
-    bool strip_form() const { return m == 256 && frame_launch == 2; }
+    bool carry_form() const { return (m == 128 && frame_launch == 2) || (m == 256 && frame_launch >= 2); }
+    bool strip_form() const { return m == 256 && frame_launch >= 2; }   // merge fused into the strip pass
+    bool colg_form() const { return m == 256 && frame_launch == 3; }    // column pass forms its own row transform
+    int carry_layout() const { return colg_form() ? sharp::CL_Q256 : sharp::CL_CB256; }
     // frame arrays (K m^2 complex values) larger than the GPU's last-level
     // cache (256 MiB on this part) are read and written with streaming
     // accesses; smaller ones stay cacheable, since a pass often finds them there

@@ -138,6 +138,14 @@ static void build_strips(sharp_plan_s& p) {
                 rec[1] = hit_row ? r : 0;
                 rec[2] = hit_row ? p.pos[2 * f + 1] : 0;
             }
+    // launch order: strips with more frame rows first (longest-processing-time
+    // order), so that the light strips at the object's edges fill the last
+    // workgroup slots instead of a heavy strip starting last
+    p.strip_order.resize(p.nstrips);
+    for (int t = 0; t < p.nstrips; ++t) p.strip_order[t] = t;
+    std::stable_sort(p.strip_order.begin(), p.strip_order.end(), [&](int a, int b) {
+        return p.strip_ptr[a + 1] - p.strip_ptr[a] > p.strip_ptr[b + 1] - p.strip_ptr[b];
+    });
 }
 
 static void choose_tuning(sharp_plan_s& p) {
@@ -166,8 +174,9 @@ static void choose_tuning(sharp_plan_s& p) {
     // unless asked otherwise; needs a strip of the object in LDS
     p.SH = p.m != 256 || p.nx > 8192 ? 0 : (p.opt.strip_rows == 2 && 2 * p.nx <= 8192) ? 2 : 1;
     p.frame_launch = p.opt.frame_launch ? p.opt.frame_launch : (p.m >= 128 ? 2 : 1);
-    if (p.m == 256 && p.frame_launch == 2 && !p.SH) p.frame_launch = 1;
+    if (p.m == 256 && p.frame_launch >= 2 && !p.SH) p.frame_launch = 1;
     if (p.m < 128) p.frame_launch = 1;
+    if (p.m == 128 && p.frame_launch == 3) p.frame_launch = 2;
     if (p.strip_form()) build_strips(p);
 }
 
@@ -185,7 +194,7 @@ static void layout(sharp_plan_s& p) {
     o.tile_ptr = take((p.ntiles + 1) * sizeof(int32_t));
     o.tile_frames = take(std::max<size_t>(p.tile_frames.size(), 1) * sizeof(int32_t));
     o.a = take(FE * sizeof(float));
-    o.a_t = take(p.m == 128 && p.carry_form() ? FE * sizeof(float) : 0);
+    o.a_t = take((p.m == 128 && p.carry_form()) || p.colg_form() ? FE * sizeof(float) : 0);
     o.u = take(FE * sizeof(float2));
     o.v = take(FE * sizeof(float2));
     o.stage = take(p.m == 256 ? FE * sizeof(float2) : 0);
@@ -213,6 +222,7 @@ static void layout(sharp_plan_s& p) {
     o.flag = take(16 * sizeof(int));
     o.sptr = take((p.strip_ptr.size() + 1) * sizeof(int32_t));
     o.sln = take((p.strip_lines.size() + 4) * sizeof(int32_t));
+    o.sord = take((p.strip_order.size() + 1) * sizeof(int32_t));
     o.total = cur;
 }
 
@@ -231,7 +241,7 @@ extern "C" int sharp_plan_create(sharp_plan* out, int nx, int ny, int m, int K, 
             if (r != 0) return SHARP_ERR_INVALID_ARG;
         if (o.periodic < 0 || o.periodic > 1 || o.probe_every < 0 || o.probe_start < 0 || !(o.eps_D >= 0.f) ||
             !(o.tile == 0 || o.tile == 16 || o.tile == 32 || o.tile == 64) || o.merge_split < 0 ||
-            o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 2 ||
+            o.merge_split > 4096 || o.grad_groups < 0 || o.frame_launch < 0 || o.frame_launch > 3 ||
             !(o.fft_block == 0 || o.fft_block == 128 || o.fft_block == 256 || o.fft_block == 512) ||
             o.strip_rows < 0 || o.strip_rows > 2 || o.probe_center < 0 || o.probe_center > 1)
             return SHARP_ERR_INVALID_ARG;
@@ -309,6 +319,8 @@ extern "C" int sharp_set_workspace(sharp_plan p, void* d, size_t bytes) {
                               hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(p->ws + p->off.sln, p->strip_lines.data(), p->strip_lines.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(p->ws + p->off.sord, p->strip_order.data(), p->strip_order.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
     }
     HIPCHK(launch_fill(p->ws + p->off.hist, kHistCap * sizeof(float), s));
     // host vectors are locals: finish the uploads before returning
@@ -373,6 +385,7 @@ MergeArgs sharp::merge_args(const sharp_plan_s& p) {
 
 int sharp::resid_blocks_default(const sharp_plan_s& p) {
     if (p.m == 128 && p.carry_form()) return fc128_groups(p.K);
+    if (p.colg_form()) return p.K * 4;
     return p.m == 256 ? p.K * 16 : (p.K + fg_groups(p.m) - 1) / fg_groups(p.m);
 }
 
@@ -394,9 +407,10 @@ extern "C" int sharp_set_data(sharp_plan p, const float* d_I) {
     if (!p || !d_I) return SHARP_ERR_INVALID_ARG;
     if (!p->has_ws) return SHARP_ERR_NOT_READY;
     int blocks = 0;
+    const bool second = (p->m == 128 && p->carry_form()) || p->colg_form();
     HIPCHK(launch_set_data(d_I, p->at<float>(p->off.a), p->frame_elems(), p->at<float>(p->off.resid),
                            p->at<int>(p->off.flag), p->stream, &blocks, p->m == 256,
-                           p->m == 128 && p->carry_form() ? p->at<float>(p->off.a_t) : nullptr));
+                           second ? p->at<float>(p->off.a_t) : nullptr, p->colg_form() ? 1 : 0));
     HIPCHK(launch_reduce(p->at<float>(p->off.resid), blocks, p->at<float>(p->off.scal), p->stream));
     p->has_data = true;
     return SHARP_OK;
@@ -470,7 +484,7 @@ static hipError_t carry_to_space(sharp_plan_s& p, float2* dst) {
     A.in = p.at<float2>(p.off.u);
     A.out = dst;
     if (p.m == 128) return launch_fc128_convert(A, 1, p.stream);
-    return launch_carry_to_space(A, p.stream);
+    return launch_carry_to_space(A, p.stream, p.carry_layout());
 }
 // frame space -> Fourier-domain carry (U = F u)
 static hipError_t space_to_carry(sharp_plan_s& p, const float2* src) {
@@ -478,7 +492,7 @@ static hipError_t space_to_carry(sharp_plan_s& p, const float2* src) {
     A.in = src;
     A.out = p.at<float2>(p.off.u);
     if (p.m == 128) return launch_fc128_convert(A, 0, p.stream);
-    return launch_space_to_carry(A, p.stream);
+    return launch_space_to_carry(A, p.stream, p.carry_layout());
 }
 // Algorithm box, step 7, after Eq. (standardprobe): the Fourier mask or
 // Fourier amplitude constraint, then the centre-of-mass correction.
@@ -511,12 +525,20 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     A.beta = beta;
     int blocks = 0;
     const Timer* t = p.tm();
-    if (p.strip_form()) {
+    if (p.colg_form()) {
+        // column pass with its own gather and row transform, then the strip
+        // merge of its k1-major rows; psi_v is final afterwards
+        const StripArgs S{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
+                          p.at<float2>(p.off.psi_v), p.SH, 0, 0, 1, p.at<int>(p.off.sord)};
+        HIPCHK(launch_colg_256(A, s, t));
+        HIPCHK(launch_strip_256(A, S, 0, p.nstrips, s, t));
+        blocks = p.K * 4;
+    } else if (p.strip_form()) {
         // frame phase and merge in one sequence; psi_v is final afterwards.  The
         // strip pass also prepares the next iteration's gather unless a probe
         // update (which reuses the stage buffer) follows.
         const StripArgs S{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
-                          p.at<float2>(p.off.psi_v), p.SH, probe_due ? 0 : 1, 0};
+                          p.at<float2>(p.off.psi_v), p.SH, probe_due ? 0 : 1, 0, 0, p.at<int>(p.off.sord)};
         if (!p.stage_gather) HIPCHK(launch_row_gather_256(A, s, t));
         HIPCHK(launch_col_carry_256(A, s, t));
         HIPCHK(launch_strip_256(A, S, 0, p.nstrips, s, t));

@@ -83,7 +83,7 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         if (!p) return SHARP_ERR_INVALID_ARG;
         for (int j = 0; j < i; ++j)
             if (plans[j] == p) return SHARP_ERR_INVALID_ARG;
-        if (p->opt.probe_every != 0) return SHARP_ERR_INVALID_ARG;
+        if (p->opt.probe_every != 0 || p->colg_form()) return SHARP_ERR_INVALID_ARG;
         if (!p->has_ws || !p->has_data || !p->has_probe || !p->has_object) return SHARP_ERR_NOT_READY;
     }
     sharp_batch_s* b = new (std::nothrow) sharp_batch_s();
@@ -114,8 +114,25 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
             if (p->split > 1)
                 for (int t = 0; t < p->ntiles; ++t) b->finish_items[tc].push_back(make_int2(s, t));
         }
-        // items are listed scan by scan: the items of scans s0 .. s1 - 1 are
-        // first[s0] .. first[s1] - 1
+        // strip items: within each chunk of scans (one launch), the strips with
+        // the most frame rows first, as in the single-scan launch order
+        {
+            auto& it2 = b->carry_items[2];
+            auto lines = [&](const int2& w) {
+                const sharp_plan_s* q = b->plans[w.x];
+                return q->strip_ptr[w.y + 1] - q->strip_ptr[w.y];
+            };
+            for (size_t c0 = 0; c0 < it2.size();) {
+                size_t c1 = c0;
+                const int chunk = it2[c0].x / kBatchChunk;
+                while (c1 < it2.size() && it2[c1].x / kBatchChunk == chunk) ++c1;
+                std::stable_sort(it2.begin() + c0, it2.begin() + c1,
+                                 [&](const int2& a, const int2& w) { return lines(a) > lines(w); });
+                c0 = c1;
+            }
+        }
+        // items are listed chunk by chunk: the items of scans s0 .. s1 - 1 (one
+        // chunk) are first[s0] .. first[s1] - 1
         auto prefix = [&](const auto& items, std::vector<int>& first) {
             first.assign(nplans + 1, 0);
             for (const auto& w : items) ++first[w.x + 1];
@@ -196,7 +213,7 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         fa[s] = frame_args(p);
         ma[s] = merge_args(p);
         sa[s] = StripArgs{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
-                          p.at<float2>(p.off.psi_v), p.SH, 1, 0};
+                          p.at<float2>(p.off.psi_v), p.SH, 1, 0, 0, nullptr};
         ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),
                         p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
     }

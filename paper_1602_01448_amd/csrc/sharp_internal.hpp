@@ -22,12 +22,27 @@ enum FrameMode : int {
     FM_GATHER = 7,  // z = g w_g T psi_v (Fourier-carry RAAR row pass, m = 256)
 };
 
+// Layouts of the m = 256 Fourier-domain carry (and of the amplitudes read with it)
+enum CarryLayout : int { CL_CB256 = 0, CL_Q256 = 1 };
+
 // For m = 256 the amplitudes (and the Fourier-domain carry) are stored
 // column-block-major: element (y, x) of a frame at ((x / 16) * 256 + y) * 16
 // + x % 16, so that a column-pass workgroup (16 columns) reads one
 // contiguous 32 KiB block.
 __host__ __device__ __forceinline__ unsigned cb256(unsigned y, unsigned x) {
     return ((x >> 4) << 12) + (y << 4) + (x & 15u);
+}
+
+// Layout of the Fourier-domain carry and the second amplitude copy of the
+// m = 256 form whose column pass forms its own row transform: the frame's
+// columns kx = k1 + 16 k2 fall into four quarters by k1 / 4 (one column-pass
+// workgroup each, 64 columns); inside a quarter, column c = 16 (k1 mod 4) + k2
+// holds its 256 rows ky = j + 16 r at c * 256 + 32 (r / 2) + 2 j + r mod 2:
+// the thread that owns rows j + 16 r of a column reads pairs (r, r + 1), and
+// the 16 threads of the column read 16 such pairs side by side.
+__host__ __device__ __forceinline__ unsigned q256(unsigned ky, unsigned kx) {
+    const unsigned k1 = kx & 15u, k2 = kx >> 4, j = ky & 15u, r = ky >> 4;
+    return ((k1 >> 2) << 14) + ((((k1 & 3u) << 4) + k2) << 8) + ((r >> 1) << 5) + (j << 1) + (r & 1u);
 }
 
 // Merge-kernel kinds
@@ -108,8 +123,10 @@ hipError_t launch_grad_probe_partial(int M, int K, const int* pos, int nx, int n
 
 // launchers (kernels_merge.hip)
 hipError_t launch_merge(int kind, const MergeArgs& a, int tiles, hipStream_t s);
+// a2: optional second amplitude copy, 128 x 128 frames transposed (a2_q256 = 0)
+// or 256 x 256 frames in the q256 layout (a2_q256 = 1)
 hipError_t launch_set_data(const float* I, float* a, size_t n, float* partials, int* flag,
-                           hipStream_t s, int* blocks_used, int blocked256, float* a_t128);
+                           hipStream_t s, int* blocks_used, int blocked256, float* a2, int a2_q256);
 hipError_t launch_reduce(const float* partials, int n, float* out, hipStream_t s);
 hipError_t launch_eps(const float* partials, int n, const float* norm_a2, float* hist, int idx,
                       int* flag, hipStream_t s);
@@ -133,7 +150,10 @@ struct StripArgs {
     int SH;                          // object rows per strip
     int next_gather;                 // also form the next iteration's gathered, row-transformed
                                      // frame rows (w * T psi_v) in the stage buffer
-    int strip0;                      // first strip of the launch (workgroup b takes strip strip0 + b)
+    int strip0;                      // first launch slot (workgroup b takes slot strip0 + b)
+    int k1major;                     // stage rows hold element k1 + 16 k2 at 16 k1 + k2 (else natural order)
+    const int* __restrict__ order;   // [nstrips] strip of each launch slot, the strips with the most frame
+                                     // rows first (nullptr: slot = strip)
 };
 size_t carry_phase_smem();
 // m = 128 with the RAAR carry kept in the Fourier domain
@@ -177,8 +197,13 @@ size_t strip_smem_bytes(int SH, int nx);
 hipError_t launch_row_gather_256(const FrameArgs& A, hipStream_t s, const Timer* t);
 hipError_t launch_col_carry_256(const FrameArgs& A, hipStream_t s, const Timer* t);
 hipError_t launch_strip_256(const FrameArgs& A, const StripArgs& S, int s0, int s1, hipStream_t s, const Timer* t);
-hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s);
-hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s);
+hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s, int layout = CL_CB256);
+hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s, int layout = CL_CB256);
+// m = 256, form 3: column pass that forms its own gathered row transform
+// (quarter-frame workgroups, carry and amplitudes in the q256 layout), writing
+// the merge input with k1-major rows to the stage buffer; one residual partial
+// per (frame, quarter), at 4 frame + quarter
+hipError_t launch_colg_256(const FrameArgs& A, hipStream_t s, const Timer* t);
 
 // batched execution (kernels_frame.hip, kernels_merge.hip)
 constexpr int kMaxBatch = 256;

@@ -75,10 +75,11 @@ def test_validation(L):
     assert _create(L, 64, 32, [(0, 0)], tile=24)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], reserved=1)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], eps_D=-1.0)[0] == -1
-    assert _create(L, 64, 32, [(0, 0)], frame_launch=3)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], frame_launch=3)[0] == 0     # taken as the small-frame form
     assert _create(L, 64, 32, [(0, 0)], fft_block=64)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], strip_rows=3)[0] == -1
     assert _create(L, 64, 32, [(0, 0)], probe_center=2)[0] == -1
+    assert _create(L, 64, 32, [(0, 0)], frame_launch=4)[0] == -1
     assert _create(L, 300, 256, [(0, 0)], fft_block=512)[0] == 0
     h = ctypes.c_void_p()
     assert L.sharp_plan_create(ctypes.byref(h), 64, 64, 32, 0, None, None) == -1
@@ -87,10 +88,13 @@ def test_validation(L):
 
 @pytest.mark.parametrize("n,kw,form,rows", [(300, {}, 2, 1), (300, {"strip_rows": 2}, 2, 2),
                                            (5000, {"strip_rows": 2}, 2, 1), (9000, {}, 1, 0),
-                                           (300, {"frame_launch": 1}, 1, 0)])
+                                           (300, {"frame_launch": 1}, 1, 0), (300, {"frame_launch": 3}, 3, 1),
+                                           (300, {"frame_launch": 3, "strip_rows": 2}, 3, 2),
+                                           (9000, {"frame_launch": 3}, 1, 0)])
 def test_large_frame_form_selection(L, n, kw, form, rows):
     """m = 256: Fourier-carry form with 1-row strips by default, 2-row strips
-    on request while a 2-row strip fits in LDS, frame-space form beyond 8192."""
+    on request while a 2-row strip fits in LDS, frame-space form beyond 8192;
+    the form whose column pass forms its own row transform on request."""
     from paper_1602_01448_amd._lib import SharpPlanInfo
     st, h = _create(L, n, 256, [(0, 0), (n - 256, n - 256)], **kw)
     assert st == 0
@@ -101,7 +105,8 @@ def test_large_frame_form_selection(L, n, kw, form, rows):
 
 
 @pytest.mark.parametrize("m,kw,form", [(128, {}, 2), (128, {"frame_launch": 1}, 1), (64, {}, 1),
-                                       (64, {"frame_launch": 2}, 1), (32, {}, 1)])
+                                       (64, {"frame_launch": 2}, 1), (32, {}, 1), (128, {"frame_launch": 3}, 2),
+                                       (64, {"frame_launch": 3}, 1)])
 def test_small_frame_form_selection(L, m, kw, form):
     """m = 128 keeps the carry in the Fourier domain by default; smaller
     frames always keep it in frame space."""

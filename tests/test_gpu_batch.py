@@ -129,6 +129,11 @@ def test_batch_rejects_probe_refinement_and_unready_plans():
     p.set_data(to_dev(_data(s))).set_probe(to_dev(c64(s.probe))).set_object(to_dev(c64(s.psi0)))
     with pytest.raises(SharpError):
         Batch([p])
+    s4 = _small_scans()[4]                      # m = 256 plan in the form batches do not run
+    q3 = Plan(s4.n, s4.n, s4.m, s4.positions, frame_launch=3)
+    q3.set_data(to_dev(_data(s4))).set_probe(to_dev(c64(s4.probe))).set_object(to_dev(c64(s4.psi0)))
+    with pytest.raises(SharpError):
+        Batch([q3])
     q = Plan(s.n, s.n, s.m, s.positions)
     with pytest.raises(SharpError):
         Batch([q])

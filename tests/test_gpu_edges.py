@@ -39,7 +39,8 @@ def _raster(ny, nx, m, gy, gx):
 
 
 @pytest.mark.parametrize("m,ny,nx,form", [(32, 96, 160, 1), (64, 320, 192, 1), (128, 200, 352, 1), (128, 352, 200, 2),
-                                          (256, 300, 700, 1), (256, 700, 300, 2)])
+                                          (256, 300, 700, 1), (256, 700, 300, 2), (256, 300, 700, 3),
+                                          (256, 700, 300, 3)])
 def test_rectangular_objects(m, ny, nx, form):
     pos = _raster(ny, nx, m, 4, 5)
     p, got, ref, D = _run(ny, nx, m, pos, frame_launch=form, seed=m + ny)
@@ -48,27 +49,28 @@ def test_rectangular_objects(m, ny, nx, form):
     assert np.max(np.abs(p.metrics() - ref["eps_a"]) / ref["eps_a"]) < 1e-4
 
 
-@pytest.mark.parametrize("m,n", [(16, 16), (32, 48), (128, 128), (256, 256), (256, 300)])
-def test_single_frame(m, n):
+@pytest.mark.parametrize("m,n,form", [(16, 16, 0), (32, 48, 0), (128, 128, 0), (256, 256, 0), (256, 300, 0),
+                                      (256, 256, 3), (256, 300, 3)])
+def test_single_frame(m, n, form):
     """One frame; for n = m it covers the whole object."""
-    p, got, ref, D = _run(n, n, m, [(n - m, n - m)], seed=m)
+    p, got, ref, D = _run(n, n, m, [(n - m, n - m)], seed=m, frame_launch=form)
     check_object(got, ref["psi"], D, 1e-4)
 
 
-@pytest.mark.parametrize("m", [32, 128, 256])
-def test_periodic_rectangular(m):
+@pytest.mark.parametrize("m,form", [(32, 0), (128, 0), (256, 0), (256, 3)])
+def test_periodic_rectangular(m, form):
     ny, nx = 2 * m + 24, 3 * m + 40
     rng = np.random.default_rng(m)
     pos = np.stack([rng.integers(0, ny, 12), rng.integers(0, nx, 12)], 1)
-    p, got, ref, D = _run(ny, nx, m, pos, periodic=True, seed=m + 1)
+    p, got, ref, D = _run(ny, nx, m, pos, periodic=True, seed=m + 1, frame_launch=form)
     check_object(got, ref["psi"], D, 1e-4)
 
 
-@pytest.mark.parametrize("m", [64, 128, 256])
-def test_probe_refinement_rectangular(m):
+@pytest.mark.parametrize("m,form", [(64, 0), (128, 0), (256, 0), (256, 3)])
+def test_probe_refinement_rectangular(m, form):
     ny, nx = 2 * m + 16, 3 * m
     pos = _raster(ny, nx, m, 4, 6)
-    p, got, ref, D = _run(ny, nx, m, pos, probe_every=1, seed=m + 2)
+    p, got, ref, D = _run(ny, nx, m, pos, probe_every=1, seed=m + 2, frame_launch=form)
     check_close(to_host(p.probe()), ref["w"], 1e-4)
     check_object(got, ref["psi"], D, 1e-4)
 
@@ -103,8 +105,8 @@ def test_data_projector_of_an_all_zero_frame(m):
     check_close(y[1], O.idft(a[1]), 1e-5, where=f"m={m} zero frame")
 
 
-@pytest.mark.parametrize("m", [32, 128, 256])
-def test_negative_intensities_are_clamped(m):
+@pytest.mark.parametrize("m,form", [(32, 0), (128, 0), (256, 0), (256, 3)])
+def test_negative_intensities_are_clamped(m, form):
     """Intensities below zero enter as amplitude 0 (a = sqrt(max(I, 0)),
     Sec. "Forward model"): the data projector and the eps_a history (whose
     norm ||a|| uses the clamped values) match the oracle."""
@@ -112,7 +114,7 @@ def test_negative_intensities_are_clamped(m):
     rng, n, pos, w, I, z, obj = _frames_case(m, 310 + m, negative=True)
     assert (I < 0).mean() > 0.1
     a = np.sqrt(np.maximum(I.astype(np.float64), 0.0))
-    p = Plan(n, n, m, pos)
+    p = Plan(n, n, m, pos, frame_launch=form)
     p.set_data(to_dev(I)).set_probe(to_dev(w))
     check_close(to_host(p.apply("PA", to_dev(z))), O.P_a(z, a), 1e-5, where=f"m={m}")
     psi0 = c64(rng.uniform(0, 1, (n, n)))
@@ -137,8 +139,8 @@ def _threshold_between(D, q=0.3):
     raise AssertionError("no gap found")
 
 
-@pytest.mark.parametrize("m", [32, 128, 256])
-def test_density_threshold(m):
+@pytest.mark.parametrize("m,form", [(32, 0), (128, 0), (256, 0), (256, 3)])
+def test_density_threshold(m, form):
     """Option eps_D > 0: (Q*Q)^{-1} is 1/D only where D > eps_D (reading R3);
     the object update and a RAAR run match the oracle with the same
     threshold, and the pixels at or below it stay exactly 0."""
@@ -147,7 +149,7 @@ def test_density_threshold(m):
     D = O.illumination_density(w, pos, (n, n))
     eps = _threshold_between(D)
     assert 0.1 < np.mean(D[D > 0] <= eps) < 0.6
-    p = Plan(n, n, m, pos, eps_D=eps)
+    p = Plan(n, n, m, pos, eps_D=eps, frame_launch=form)
     p.set_data(to_dev(I)).set_probe(to_dev(w))
     got = to_host(p.apply("OBJECT", to_dev(z)))
     check_close(got, O.object_update(z, w, pos, (n, n), eps_D=eps), 1e-5, where=f"m={m}")

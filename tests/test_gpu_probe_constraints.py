@@ -38,10 +38,10 @@ def _lowpass(m):
     return (np.hypot(f[:, None], f[None, :]) < m / 4).astype(np.float64)
 
 
-def _run(m, n, pos, I, psi0, w0, n_iter, **kw):
+def _run(m, n, pos, I, psi0, w0, n_iter, form=0, **kw):
     from paper_1602_01448_amd import Plan
     center = kw.pop("center", False)
-    p = Plan(n, n, m, pos, probe_every=1, probe_center=center)
+    p = Plan(n, n, m, pos, probe_every=1, probe_center=center, frame_launch=form)
     p.set_data(to_dev(I.astype(np.float32))).set_probe(to_dev(c64(w0)))
     if "mask" in kw:
         p.set_probe_constraint(mask=to_dev(kw["mask"].astype(np.float32)))
@@ -51,9 +51,9 @@ def _run(m, n, pos, I, psi0, w0, n_iter, **kw):
     return to_host(p.object()), to_host(p.probe())
 
 
-@pytest.mark.parametrize("m", [64, 128, 256])
+@pytest.mark.parametrize("m,form", [(64, 0), (128, 0), (256, 0), (256, 3)])
 @pytest.mark.parametrize("kind", ["mask", "amplitudes", "center"])
-def test_probe_constraint_matches_oracle(m, kind):
+def test_probe_constraint_matches_oracle(m, form, kind):
     # centre-of-mass case: a probe centred a quarter pixel off the frame
     # centre, so that the corrected centroids stay clear of the half-pixel
     # ties at m/2 +- 1/2 (checked below)
@@ -79,7 +79,7 @@ def test_probe_constraint_matches_oracle(m, kind):
             for v in c:
                 f = (m // 2 - v + 0.5) % 1.0
                 assert min(f, 1.0 - f) >= 0.05, (m, c)
-    psi, w = _run(m, n, pos, I, psi0, w0, 3, **kw)
+    psi, w = _run(m, n, pos, I, psi0, w0, 3, form, **kw)
     D = O.illumination_density(ref["w"], pos, (n, n))
     check_close(w, ref["w"], 1e-4)
     check_object(psi, ref["psi"], D, 1e-4)

@@ -133,7 +133,8 @@ def test_large_frames_one_iteration_sampled():
 
 @pytest.mark.slow
 @pytest.mark.timeout(900)
-def test_large_frames_three_iterations_full_object():
+@pytest.mark.parametrize("form", [0, 3])
+def test_large_frames_three_iterations_full_object(form):
     """Full 2048^2 / 2025 x 256^2 scan with Poisson data, in the launch
     configuration the benchmark times (tuned plan: Fourier-domain carry,
     streaming accesses): the whole object after three iterations and the
@@ -144,8 +145,8 @@ def test_large_frames_three_iterations_full_object():
     I, c = _data(s)
     w = c64(np.sqrt(c) * s.probe)
     psi0 = c64(s.psi0)
-    p = Plan.tuned(s.n, s.n, s.m, s.positions)
-    assert p.info()["frame_launch"] == 2 and p.info()["streaming"] == 1
+    p = Plan.tuned(s.n, s.n, s.m, s.positions, **({"frame_launch": form} if form else {}))
+    assert p.info()["frame_launch"] in (2, 3) and p.info()["streaming"] == 1
     p.set_data(to_dev(I)).set_probe(to_dev(w)).set_object(to_dev(psi0)).raar(3, s.beta)
     got, eps = to_host(p.object()), p.metrics()
     del p
@@ -289,11 +290,13 @@ def test_large_frame_pass_block_sizes(block):
     assert np.max(np.abs(got["eps"] - ref["eps_a"]) / ref["eps_a"]) < 1e-4
 
 
-@pytest.mark.parametrize("form,rows", [(1, 0), (2, 1), (2, 2)])
+@pytest.mark.parametrize("form,rows", [(1, 0), (2, 1), (2, 2), (3, 1), (3, 2)])
 @pytest.mark.parametrize("periodic", [False, True])
 def test_large_frame_forms_match_oracle(form, rows, periodic):
-    """Both m = 256 forms (frame-space carry + tile merge; Fourier-domain carry
-    + strip merge) against the oracle, with and without periodic wrap."""
+    """Every m = 256 form (frame-space carry + tile merge; Fourier-domain carry
+    + strip merge; Fourier-domain carry with the column pass forming its own
+    row transform + strip merge) against the oracle, with and without
+    periodic wrap."""
     rng = np.random.default_rng(5 + form)
     n, m = 704, 256
     if periodic:
@@ -308,7 +311,7 @@ def test_large_frame_forms_match_oracle(form, rows, periodic):
     assert np.max(np.abs(got["eps"] - ref["eps_a"]) / ref["eps_a"]) < 1e-4
 
 
-@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("form", [1, 2, 3])
 def test_large_frame_probe_refinement(form):
     rng = np.random.default_rng(11)
     n, m = 640, 256
@@ -320,8 +323,9 @@ def test_large_frame_probe_refinement(form):
     check_object(got["psi"], ref["psi"], D, 1e-4)
 
 
-def test_large_frame_checkpoint_resume():
-    """Fourier-carry form: the state holds the carry in frame space; resuming
+@pytest.mark.parametrize("form", [2, 3])
+def test_large_frame_checkpoint_resume(form):
+    """Fourier-carry forms: the state holds the carry in frame space; resuming
     continues the run to rounding (the carry is transformed back and forth)."""
     rng = np.random.default_rng(12)
     n, m = 640, 256
@@ -331,13 +335,14 @@ def test_large_frame_checkpoint_resume():
     I = O.forward_intensity(obj, probe, pos).astype(np.float32)
     psi0 = c64(rng.uniform(0, 1, (n, n)))
     from paper_1602_01448_amd import Plan
-    p = Plan(n, n, m, pos)
+    p = Plan(n, n, m, pos, frame_launch=form)
+    assert p.info()["frame_launch"] == form
     p.set_data(to_dev(I)).set_probe(to_dev(c64(probe))).set_object(to_dev(psi0)).raar(6, 0.75)
     full = to_host(p.object())
-    q = Plan(n, n, m, pos)
+    q = Plan(n, n, m, pos, frame_launch=form)
     q.set_data(to_dev(I)).set_probe(to_dev(c64(probe))).set_object(to_dev(psi0)).raar(3, 0.75)
     st = q.state().clone()
-    r = Plan(n, n, m, pos)
+    r = Plan(n, n, m, pos, frame_launch=form)
     r.set_data(to_dev(I)).load_state(st).raar(3, 0.75)
     D = O.illumination_density(probe, pos, (n, n))
     check_object(to_host(r.object()), full, D, 1e-5)
