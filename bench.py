@@ -40,7 +40,9 @@ def algorithmic_bytes(K: int, m: int, n: int, form: int = 1) -> dict:
     fp = K * m * m
     op = n * n
     out = {"iteration": 36 * fp + 20 * op}
-    if m == 256 and form == 2:   # Fourier-domain carry: gather + rows, columns with the carry, strip merge
+    if m == 256 and form == 3:   # Fourier-domain carry: columns with their own gather and rows, strip merge
+        out.update({"cols": 28 * fp + 8 * op, "merge": 8 * fp + 12 * op})
+    elif m == 256 and form == 2:  # Fourier-domain carry: gather + rows, columns with the carry, strip merge
         out.update({"frame": 8 * op, "cols": 28 * fp, "merge": 8 * fp + 12 * op})
     elif m == 256:               # three passes: row (carry + gather), column (amplitudes), output row (writes)
         out.update({"frame": 8 * fp + 8 * op, "cols": 4 * fp, "frame_out": 16 * fp, "merge": 8 * fp + 12 * op})
@@ -50,6 +52,8 @@ def algorithmic_bytes(K: int, m: int, n: int, form: int = 1) -> dict:
 
 
 def kernel_names(m: int, form: int) -> dict:
+    if m == 256 and form == 3:
+        return {"cols": "colg_kernel", "merge": "strip_merge_kernel"}
     if m == 256 and form == 2:
         return {"frame": "mp_row_fwd<256, GATHER>", "cols": "col_carry_kernel<true>", "merge": "strip_merge_kernel"}
     if m == 256:

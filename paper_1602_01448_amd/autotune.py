@@ -4,8 +4,9 @@ Times candidate launch configurations of the library on the GPU and keeps the
 fastest per geometry:
 
 * the form of the iteration for 128 x 128 and 256 x 256 frames (carry in
-  the Fourier domain or in frame space), for the 256 x 256 Fourier-carry
-  form the strip height of the fused merge (1 or 2 object rows), and for the
+  the Fourier domain or in frame space; at 256 x 256 also whether the column
+  pass forms its own row transform), for the 256 x 256 Fourier-carry forms
+  the strip height of the fused merge (1 or 2 object rows), and for the
   256 x 256 frame-space form the pass workgroup size (128, 256 or 512
   threads, i.e. 8, 16 or 32 rows / columns of a frame per workgroup);
 * merge tile side (16, 32, 64) and frame-chunk split of the overlap merge,
@@ -86,7 +87,7 @@ def _merge_candidates(n: int):
 
 def _frame_candidates(m: int):
     if m == 256:
-        return ([{"frame_launch": 2, "strip_rows": r} for r in (1, 2)]
+        return ([{"frame_launch": f, "strip_rows": r} for f in (3, 2) for r in (1, 2)]
                 + [{"frame_launch": 1, "fft_block": b} for b in (128, 256, 512)])
     if m == 128:
         return [{"frame_launch": 2}, {"frame_launch": 1}]
@@ -94,9 +95,9 @@ def _frame_candidates(m: int):
 
 
 def _uses_tile_merge(m: int, frame_opts: dict) -> bool:
-    """Every form except the 256 x 256 Fourier-carry form (whose merge is
-    fused into its strip pass) ends with the tile merge."""
-    return not (m == 256 and frame_opts.get("frame_launch") == 2)
+    """Every form except the 256 x 256 Fourier-carry forms (whose merge is
+    fused into their strip pass) ends with the tile merge."""
+    return not (m == 256 and frame_opts.get("frame_launch") in (2, 3))
 
 
 def _synthetic(plan: Plan, seed: int):

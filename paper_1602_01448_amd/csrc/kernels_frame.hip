@@ -1775,28 +1775,44 @@ __device__ float colg_item(const FrameArgs& A, int frame, int quarter, float2* l
     return op.resid;
 }
 
-// Workgroup b: XCD b mod 8 takes frames [x F, (x + 1) F) in order (F = ceil(K / 8)),
-// the four quarters of a frame one after another, so that a frame's object
-// window and its neighbours' stay in that XCD's L2 while they are reused.
-template <bool STREAM>
-__global__ void __launch_bounds__(1024) colg_kernel(FrameArgs A) {
-    extern __shared__ float2 smem[];
-    __shared__ float red[16];
-    float2* lds = smem;
-    float2* twl = smem + colg::QE;   // W^t, t < 256, then the padded table T[j][r] = W^(j r) at 256 + 17 j + r
+// Item b (of 32 ceil(K / 8)): XCD b mod 8 takes frames [x F, (x + 1) F) in order
+// (F = ceil(K / 8)), the four quarters of a frame one after another, so that a
+// frame's object window and its neighbours' stay in that XCD's L2 while they
+// are reused.  Items past the last frame do nothing.
+__device__ __forceinline__ void colg_run(const FrameArgs& A, int item, float2* lds, float* red) {
+    float2* twl = lds + colg::QE;   // W^t, t < 256, then the padded table T[j][r] = W^(j r) at 256 + 17 j + r
     for (int t = threadIdx.x; t < 256; t += 1024) twl[t] = A.tw[t];
     for (int t = threadIdx.x; t < colg::TW17; t += 1024) {
         const int j = t / 17, r = t % 17;
         twl[256 + t] = A.tw[(j * r) & 255];
     }
     const int fpx = (A.K + 7) >> 3;
-    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int xcd = item & 7, local = item >> 3;
     const int frame = xcd * fpx + (local >> 2), quarter = local & 3;
     if (frame >= A.K) return;
     __syncthreads();
-    const float r = colg_item<STREAM>(A, frame, quarter, lds, twl);
+    const float r = A.stream ? colg_item<true>(A, frame, quarter, lds, twl) : colg_item<false>(A, frame, quarter, lds, twl);
     const float s = block_sum(r, red);
     if (threadIdx.x == 0) A.resid[4 * frame + quarter] = s;
+}
+
+__global__ void __launch_bounds__(1024) colg_kernel(FrameArgs A) {
+    extern __shared__ float2 smem[];
+    __shared__ float red[16];
+    colg_run(A, blockIdx.x, smem, red);
+}
+
+// Batched form: one (scan, item) per workgroup, the single-scan arithmetic and
+// item mapping.
+__global__ void __launch_bounds__(1024) batch_colg_kernel(const BatchArgs CH, const FrameArgs* __restrict__ D,
+                                                          const int2* __restrict__ items, int n) {
+    extern __shared__ float2 smem[];
+    __shared__ float red[16];
+    const int it = blockIdx.x;
+    if (it >= n) return;
+    const int2 w = items[it];
+    const FrameArgs A = batch_args(CH, D, w.x);
+    colg_run(A, w.y, smem, red);
 }
 
 size_t colg_smem() { return (size_t)(colg::QE + 256 + colg::TW17) * sizeof(float2); }
@@ -2086,7 +2102,9 @@ __global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(co
         const float s = block_sum(r, red);
         if (threadIdx.x == 0) A.resid[w.y] = s;
     } else {
-        strip_merge_item<false>(A, CH.s[w.x - CH.base], w.y, lds, twl, twl + 256);
+        const StripArgs& S = CH.s[w.x - CH.base];
+        if (S.k1major) strip_merge_item<true>(A, S, w.y, lds, twl, twl + 256);
+        else strip_merge_item<false>(A, S, w.y, lds, twl, twl + 256);
     }
 }
 
@@ -2224,23 +2242,31 @@ hipError_t launch_col_carry_256(const FrameArgs& A, hipStream_t s, const Timer* 
     return hipGetLastError();
 }
 
+int colg_items(int K) { return 32 * ((K + 7) / 8); }
+
+hipError_t batch_colg_prepare() {
+    return hipFuncSetAttribute((const void*)batch_colg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)colg_smem());
+}
+
+hipError_t launch_batch_colg(const BatchArgs& C, const FrameArgs* D, const int2* items, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_colg_kernel, dim3(n), dim3(1024), colg_smem(), s, C, D, items, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_colg_256(const FrameArgs& A, hipStream_t s, const Timer* tp) {
     const Timer& t = tp ? *tp : kNoTimer;
     if (A.K <= 0) return hipSuccess;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)colg_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        hipError_t e = hipFuncSetAttribute((const void*)colg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)colg_smem());
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)colg_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)colg_smem());
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int grid = 32 * ((A.K + 7) / 8);
     t.begin(TC_COLS, s);
-    if (A.stream) hipLaunchKernelGGL(colg_kernel<true>, dim3(grid), dim3(1024), colg_smem(), s, A);
-    else hipLaunchKernelGGL(colg_kernel<false>, dim3(grid), dim3(1024), colg_smem(), s, A);
+    hipLaunchKernelGGL(colg_kernel, dim3(colg_items(A.K)), dim3(1024), colg_smem(), s, A);
     t.end(TC_COLS, s);
     return hipGetLastError();
 }

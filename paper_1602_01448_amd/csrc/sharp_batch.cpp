@@ -45,15 +45,16 @@ struct sharp_batch_s {
     std::vector<int2> frame_items[5];     // per frame-size class (m = 256: frame-space carry form)
     std::vector<int4> merge_items[3];     // per merge-tile class
     std::vector<int2> finish_items[3];
-    std::vector<int2> carry_items[3];     // m = 256 Fourier-carry form: rows, columns, strips
+    std::vector<int2> carry_items[3];     // m = 256 Fourier-carry forms: rows, columns (form 2), strips
+    std::vector<int2> colg_items;         // m = 256 form 3: column pass with its own row transform
     // first item of each scan in every list (prefix sums, nplans + 1 entries)
-    std::vector<int> frame_first[5], merge_first[3], finish_first[3], carry_first[3], fc_first;
+    std::vector<int> frame_first[5], merge_first[3], finish_first[3], carry_first[3], fc_first, colg_first;
     std::vector<BatchArgs> arg_chunks;          // argument blocks by value, kBatchChunk scans each
     std::vector<BatchMergeArgs> merge_chunks;
     std::vector<int2> fc_items;           // m = 128 Fourier-carry form: (scan, frame group)
     size_t carry_smem = 0;                // LDS of the strip phase (widest object)
     struct {
-        size_t fargs, eps, fitems[5], mitems[3], fin[3], citems[3], fcitems, total;
+        size_t fargs, eps, fitems[5], mitems[3], fin[3], citems[3], fcitems, gitems, total;
     } off{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -83,7 +84,7 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         if (!p) return SHARP_ERR_INVALID_ARG;
         for (int j = 0; j < i; ++j)
             if (plans[j] == p) return SHARP_ERR_INVALID_ARG;
-        if (p->opt.probe_every != 0 || p->colg_form()) return SHARP_ERR_INVALID_ARG;
+        if (p->opt.probe_every != 0) return SHARP_ERR_INVALID_ARG;
         if (!p->has_ws || !p->has_data || !p->has_probe || !p->has_object) return SHARP_ERR_NOT_READY;
     }
     sharp_batch_s* b = new (std::nothrow) sharp_batch_s();
@@ -92,6 +93,12 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         for (int s = 0; s < nplans; ++s) {
             sharp_plan_s* p = plans[s];
             b->plans.push_back(p);
+            if (p->colg_form()) {
+                for (int it = 0; it < colg_items(p->K); ++it) b->colg_items.push_back(make_int2(s, it));
+                for (int st = 0; st < p->nstrips; ++st) b->carry_items[2].push_back(make_int2(s, st));
+                b->carry_smem = std::max(b->carry_smem, strip_smem_bytes(p->SH, p->nx));
+                continue;
+            }
             if (p->strip_form()) {
                 for (int it = 0; it < p->K * 16; ++it) {
                     b->carry_items[0].push_back(make_int2(s, it));
@@ -145,6 +152,7 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
             prefix(b->carry_items[c], b->carry_first[c]);
         }
         prefix(b->fc_items, b->fc_first);
+        prefix(b->colg_items, b->colg_first);
         size_t cur = 0;
         auto take = [&](size_t bytes) {
             size_t at = cur;
@@ -155,6 +163,7 @@ extern "C" int sharp_batch_create(sharp_batch* out, int nplans, const sharp_plan
         b->off.eps = take(nplans * sizeof(EpsDesc));
         for (int c = 0; c < 3; ++c) b->off.citems[c] = take(b->carry_items[c].size() * sizeof(int2));
         b->off.fcitems = take(b->fc_items.size() * sizeof(int2));
+        b->off.gitems = take(b->colg_items.size() * sizeof(int2));
         for (int c = 0; c < 5; ++c) b->off.fitems[c] = take(b->frame_items[c].size() * sizeof(int2));
         for (int c = 0; c < 3; ++c) {
             b->off.mitems[c] = take(b->merge_items[c].size() * sizeof(int4));
@@ -212,8 +221,9 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         sharp_plan_s& p = *b->plans[s];
         fa[s] = frame_args(p);
         ma[s] = merge_args(p);
+        // form 3: the column pass gathers for itself and leaves k1-major rows
         sa[s] = StripArgs{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
-                          p.at<float2>(p.off.psi_v), p.SH, 1, 0, 0, nullptr};
+                          p.at<float2>(p.off.psi_v), p.SH, p.colg_form() ? 0 : 1, 0, p.colg_form() ? 1 : 0, nullptr};
         ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),
                         p.at<float>(p.off.hist), p.at<int>(p.off.flag)};
     }
@@ -237,6 +247,9 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
     if (!b->fc_items.empty())
         HIPCHK(hipMemcpyAsync(b->ws + b->off.fcitems, b->fc_items.data(), b->fc_items.size() * sizeof(int2),
                               hipMemcpyHostToDevice, st));
+    if (!b->colg_items.empty())
+        HIPCHK(hipMemcpyAsync(b->ws + b->off.gitems, b->colg_items.data(), b->colg_items.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, st));
     for (int c = 0; c < 5; ++c)
         if (!b->frame_items[c].empty())
             HIPCHK(hipMemcpyAsync(b->ws + b->off.fitems[c], b->frame_items[c].data(),
@@ -259,6 +272,7 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         if (!b->carry_items[ph].empty()) HIPCHK(batch_carry_prepare(ph, smem, &per));
     }
     if (!b->fc_items.empty()) HIPCHK(batch_fc128_prepare(&per));
+    if (!b->colg_items.empty()) HIPCHK(batch_colg_prepare());
     return SHARP_OK;
 }
 
@@ -298,6 +312,9 @@ static int enqueue_iterations(sharp_batch_s& b, int n, float beta, hipStream_t s
                 return launch_batch_carry(ph, b.arg_chunks[k], D, b.at<int2>(b.off.citems[ph]) + i0, cnt,
                                           carry_phase_smem(), s);
             });
+        CHUNKS(b.colg_first, [&](int k, int i0, int cnt) {
+            return launch_batch_colg(b.arg_chunks[k], D, b.at<int2>(b.off.gitems) + i0, cnt, s);
+        });
         HIPCHK(launch_batch_eps(E, D, ns, beta, s));
         CHUNKS(b.carry_first[2], [&](int k, int i0, int cnt) {
             return launch_batch_carry(2, b.arg_chunks[k], D, b.at<int2>(b.off.citems[2]) + i0, cnt, b.carry_smem, s);
@@ -367,7 +384,7 @@ extern "C" int sharp_batch_raar_iterate(sharp_batch b, int n, float beta) {
         p->hist_count += n;
         p->g = beta;
         p->last_probe_updated = false;
-        p->stage_gather = p->strip_form();
+        p->stage_gather = p->strip_form() && !p->colg_form();
     }
     return SHARP_OK;
 }

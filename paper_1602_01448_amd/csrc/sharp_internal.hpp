@@ -191,6 +191,9 @@ hipError_t launch_batch_carry(int phase, const BatchArgs& C, const FrameArgs* D,
                               size_t smem, hipStream_t s);
 // items: (scan, frame group slot) of the chunk's scans, one workgroup each
 hipError_t launch_batch_fc128(const BatchArgs& C, const FrameArgs* D, const int2* items, int n, hipStream_t s);
+// items: (scan, item < colg_items(K)) of the chunk's form-3 scans, one workgroup each
+hipError_t batch_colg_prepare();
+hipError_t launch_batch_colg(const BatchArgs& C, const FrameArgs* D, const int2* items, int n, hipStream_t s);
 size_t strip_smem_bytes(int SH, int nx);
 // m = 256 Fourier-carry form: gather + row transforms (first iteration only),
 // column pass over the K frames of A, strip pass over strips [s0, s1)
@@ -204,6 +207,7 @@ hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s, int layout =
 // the merge input with k1-major rows to the stage buffer; one residual partial
 // per (frame, quarter), at 4 frame + quarter
 hipError_t launch_colg_256(const FrameArgs& A, hipStream_t s, const Timer* t);
+int colg_items(int K);   // workgroups (items) of one launch over K frames
 
 // batched execution (kernels_frame.hip, kernels_merge.hip)
 constexpr int kMaxBatch = 256;

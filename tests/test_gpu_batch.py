@@ -23,9 +23,9 @@ def _small_scans():
     return out
 
 
-def _plan(s, I):
+def _plan(s, I, **kw):
     from paper_1602_01448_amd import Plan
-    p = Plan(s.n, s.n, s.m, s.positions)
+    p = Plan(s.n, s.n, s.m, s.positions, **kw)
     p.set_data(to_dev(I)).set_probe(to_dev(c64(s.probe))).set_object(to_dev(c64(s.psi0)))
     return p
 
@@ -129,11 +129,7 @@ def test_batch_rejects_probe_refinement_and_unready_plans():
     p.set_data(to_dev(_data(s))).set_probe(to_dev(c64(s.probe))).set_object(to_dev(c64(s.psi0)))
     with pytest.raises(SharpError):
         Batch([p])
-    s4 = _small_scans()[4]                      # m = 256 plan in the form batches do not run
-    q3 = Plan(s4.n, s4.n, s4.m, s4.positions, frame_launch=3)
-    q3.set_data(to_dev(_data(s4))).set_probe(to_dev(c64(s4.probe))).set_object(to_dev(c64(s4.psi0)))
-    with pytest.raises(SharpError):
-        Batch([q3])
+
     q = Plan(s.n, s.n, s.m, s.positions)
     with pytest.raises(SharpError):
         Batch([q])
@@ -168,3 +164,30 @@ def test_batch_refuses_a_plan_moved_to_another_workspace():
     b.raar(3, 0.75)
     single = _plan(scans[1], data[1]).raar(3, 0.75)
     assert np.array_equal(to_host(single.object()), to_host(p.object()))
+
+
+def test_batch_large_frame_forms_bitwise():
+    """m = 256 scans in both Fourier-carry forms (form 3: column pass with its
+    own row transform) batched with smaller scans: batched = single, bit for
+    bit, and the form-3 scan against the oracle."""
+    from paper_1602_01448_amd import Batch
+    scans = _small_scans()
+    rng = np.random.default_rng(808)
+    n, m = 448, 256
+    big = gen.Scan("f3", n, m, gen.raster_positions(4, 64.0, n, m, jitter=2, rng=rng), gen.random_object(rng, n, n),
+                   gen.gaussian_probe(m, 48.0), rng.uniform(0, 1, (n, n)).astype(complex), None, 0.75, 3, 0, 1,
+                   False, None)
+    cases = [(scans[4], 3), (big, 3), (big, 2), (scans[1], 0), (scans[3], 0)]
+    data = [_data(s) for s, _ in cases]
+    single = [_plan(s, I, frame_launch=f) for (s, f), I in zip(cases, data)]
+    batched = [_plan(s, I, frame_launch=f) for (s, f), I in zip(cases, data)]
+    assert [p.info()["frame_launch"] for p in single[:3]] == [3, 3, 2]
+    for p in single:
+        p.raar(3, 0.75)
+    Batch(batched).raar(3, 0.75)
+    for (s, f), p, q in zip(cases, single, batched):
+        assert np.array_equal(to_host(p.object()), to_host(q.object())), (s.name, f)
+        assert np.array_equal(p.metrics(), q.metrics()), (s.name, f)
+    ref = O.raar(data[1].astype(np.float64), big.positions, (n, n), m, 3, 0.75, psi0=c64(big.psi0), w0=c64(big.probe))
+    D = O.illumination_density(big.probe, big.positions, (n, n))
+    check_object(to_host(batched[1].object()), ref["psi"], D, 1e-4)
