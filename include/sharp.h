@@ -71,14 +71,21 @@ typedef struct sharp_options {
     int tile;         /* merge tile side in object pixels: 16, 32 or 64 (0 = tuned) */
     int merge_split;  /* frame chunks per tile in the first merge pass, >= 1 (0 = tuned) */
     int grad_groups;  /* workgroups of the gradient frame kernel (0 = tuned) */
-    int frame_launch; /* m = 256 RAAR: 0 = default (2 when the object is at most 8192
-                         wide, else 1); 1 = row, column and row passes with the carry in
-                         frame space, then the tile merge; 2 = carry kept in the Fourier
-                         domain, merge fused into the last (inverse row) pass */
+    int frame_launch; /* m = 128: 0 or 2 = carry kept in the Fourier domain (default),
+                         1 = carry in frame space (3 is taken as 2).  m = 256 RAAR:
+                         0 = default (3 when K >= 768, else 2; 1 when the object is
+                         wider than 8192); 1 = row, column and row passes with the carry
+                         in frame space, then the tile merge; 2 = carry kept in the
+                         Fourier domain, a column pass reading the row-transformed
+                         gather that the previous strip merge prepared; 3 = carry in
+                         the Fourier domain, the column pass (a quarter of a frame's
+                         columns per workgroup) forms its own row transform and the
+                         strip merge only merges.  m < 128: ignored (frame space).
+                         Values outside 0..3 are rejected */
     int fft_block;    /* m = 256, form 1: threads per pass workgroup, 128, 256 or 512 (8, 16
                          or 32 rows / columns per workgroup); 0 = 256 */
-    int strip_rows;   /* m = 256, form 2: object rows per merge strip, 1 or 2 (0 = default,
-                         1); 2 is taken only while 2 nx <= 8192 */
+    int strip_rows;   /* m = 256, forms 2 and 3: object rows per merge strip, 1 or 2 (0 =
+                         default, 1); 2 is taken only while 2 nx <= 8192 */
     int probe_center; /* 1: after every probe update, roll the probe circularly by the integer
                          that brings the centroid of |w|^2 within half a pixel of (m/2, m/2)
                          (algorithm box, step 7, centre-of-mass drift correction); 0: off */

@@ -12,7 +12,9 @@ from ctypes import POINTER, Structure, c_char_p, c_float, c_int, c_int32, c_long
 import torch  # noqa: F401  (must precede loading the library: shared HIP runtime)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsharp.so")
+# SHARP_LIBRARY selects another build of the same sources (for instance the
+# host-sanitizer build the CPU tests make); default: the in-tree library
+LIB_PATH = os.environ.get("SHARP_LIBRARY") or os.path.join(HERE, "libsharp.so")
 
 SHARP_OK = 0
 STATUS = {

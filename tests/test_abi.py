@@ -90,13 +90,18 @@ def test_validation(L):
                                            (5000, {"strip_rows": 2}, 2, 1), (9000, {}, 1, 0),
                                            (300, {"frame_launch": 1}, 1, 0), (300, {"frame_launch": 3}, 3, 1),
                                            (300, {"frame_launch": 3, "strip_rows": 2}, 3, 2),
-                                           (9000, {"frame_launch": 3}, 1, 0)])
+                                           (9000, {"frame_launch": 3}, 1, 0), (-300, {}, 3, 1),
+                                           (-300, {"frame_launch": 2}, 2, 1), (-9000, {}, 1, 0)])
 def test_large_frame_form_selection(L, n, kw, form, rows):
     """m = 256: Fourier-carry form with 1-row strips by default, 2-row strips
     on request while a 2-row strip fits in LDS, frame-space form beyond 8192;
-    the form whose column pass forms its own row transform on request."""
+    the form whose column pass forms its own row transform on request, and
+    by default from 768 frames on (n < 0: 800 frames)."""
     from paper_1602_01448_amd._lib import SharpPlanInfo
-    st, h = _create(L, n, 256, [(0, 0), (n - 256, n - 256)], **kw)
+    K = 800 if n < 0 else 2
+    n = abs(n)
+    pos = [(0, 0)] * (K - 1) + [(n - 256, n - 256)]
+    st, h = _create(L, n, 256, pos, **kw)
     assert st == 0
     info = SharpPlanInfo()
     assert L.sharp_get_plan_info(h, ctypes.byref(info)) == 0
