@@ -495,10 +495,49 @@ def cpu_baseline(budget_rows: int = 9, iters: int = 3) -> dict:
     frames = len(sel) * iters
     sample = (f"{len(sel)} frames of 256x256 (first {budget_rows} raster rows of the large-frame scan, "
               f"{ny}x{s.n} object strip), {iters} RAAR iterations incl. set-up, FP64")
+    with threadpool_limits(limits=1):
+        others = cpu_other_workloads()
     return {"value": round(frames / dt1, 3), "unit": "frames/s", "cores": 1, "kind": "oracle",
             "sample": sample + ", NumPy, one thread", "cpu_model": _cpu_model(), "host_cores": host_cores,
             "variants": [{"kind": "oracle, F and F* by scipy.fft on every host core", "value": round(frames / dtn, 3),
-                          "unit": "frames/s", "cores": host_cores}]}
+                          "unit": "frames/s", "cores": host_cores}],
+            "other_workloads": others}
+
+
+def cpu_other_workloads() -> list:
+    """The FP64 oracle, one thread, on the other bench workloads in full (a few
+    seconds each): plain small RAAR, RAAR with probe refinement every
+    iteration, one gradient evaluation.  Times include the oracle's set-up."""
+    import numpy as np
+
+    import oracle as O
+    from sharp_data import gen
+
+    out = []
+    s = gen.config_scan(1)
+    I = O.forward_intensity(s.obj, s.probe, s.positions)
+    t = time.perf_counter()
+    O.raar(I, s.positions, (s.n, s.n), s.m, 10, s.beta, psi0=s.psi0, w0=s.probe)
+    dt = time.perf_counter() - t
+    out.append({"workload": "plain RAAR: object 128x128, 169 frames 32x32, 10 iterations",
+                "value": round(len(s.positions) * 10 / dt, 1), "unit": "frames/s", "cores": 1})
+    s = gen.config_scan(2)
+    I = O.forward_intensity(s.obj, s.probe, s.positions)
+    t = time.perf_counter()
+    O.raar(I, s.positions, (s.n, s.n), s.m, 3, s.beta, psi0=s.psi0, probe_every=1)
+    dt = time.perf_counter() - t
+    out.append({"workload": "RAAR + probe refinement every iteration: object 512x512, 841 frames 64x64, "
+                            "probe from the data, 3 iterations",
+                "value": round(len(s.positions) * 3 / dt, 1), "unit": "frames/s", "cores": 1})
+    s = gen.config_scan(4)
+    psi, w = gen.gradient_point(s)
+    a = np.sqrt(O.forward_intensity(s.obj, s.probe, s.positions))
+    t = time.perf_counter()
+    O.amplitude_grad(psi, w, s.positions, a)
+    dt = time.perf_counter() - t
+    out.append({"workload": "gradient: object 512x512, 1024 frames 128x128, one evaluation",
+                "value": round(len(s.positions) / dt, 1), "unit": "frames/s", "cores": 1})
+    return out
 
 
 def main() -> int:
