@@ -1686,8 +1686,12 @@ __device__ __forceinline__ void colg_inner_sums(const FrameArgs& A, int py, int 
     }
 }
 
+// One quarter-frame item; writes its residual partial A.resid[4 frame + quarter]
+// (wave sums in red[], added by thread 0 in wave order once the barrier after
+// the inverse column transforms has made them visible).  The workgroup takes
+// no further item, so it ends without a closing barrier.
 template <bool STREAM>
-__device__ float colg_item(const FrameArgs& A, int frame, int quarter, float2* lds, const float2* twl) {
+__device__ void colg_item(const FrameArgs& A, int frame, int quarter, float2* lds, const float2* twl, float* red) {
     using namespace colg;
     const int tid = opaque_tid();
     const int py = A.pos[2 * frame], px = A.pos[2 * frame + 1];
@@ -1697,6 +1701,26 @@ __device__ float colg_item(const FrameArgs& A, int frame, int quarter, float2* l
     if (A.periodic) colg_inner_sums<true>(A, py, px, quarter, lds, twl);
     else colg_inner_sums<false>(A, py, px, quarter, lds, twl);
     __syncthreads();
+    // carry and amplitudes of rows j + 16 q of column col (q256 layout: the
+    // pair q, q + 1 of every thread of the column lies side by side, so a
+    // request of the 16 threads covers 256 contiguous bytes); the amplitudes
+    // and the first half of the carry are requested here, ahead of the DFTs
+    // over n2 and the forward column transform (earlier, during the inner
+    // sums, they do not fit the register budget), the second half in the
+    // pointwise loop
+    const int col = tid >> 4, j = tid & 15;
+    const size_t qb = (size_t)frame * MM + (size_t)quarter * QE;
+    const unsigned cofs = (unsigned)col * M + 2u * j;
+    float2 uc[8];
+    float ac[16];
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+        const float2 t = ldf2t<STREAM>(A.at + qb, cofs + 16 * q);
+        ac[q] = t.x;
+        ac[q + 1] = t.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) ld2t<STREAM>(A.u + qb, cofs + 16 * q, uc[q], uc[q + 1]);
     // ---- sixteen-point DFTs over n2: G[y][4 quarter + i + 16 k2] ------------
     {
         const int y = tid & 255, i = tid >> 8;
@@ -1710,28 +1734,10 @@ __device__ float colg_item(const FrameArgs& A, int frame, int quarter, float2* l
     }
     __syncthreads();
     // ---- columns ------------------------------------------------------------
-    const int col = tid >> 4, j = tid & 15;
     auto at = [col](int p) { return colg::l2(col, p); };
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = lds[at(j + 16 * r)];
-    // carry and amplitudes of rows j + 16 q of this column (q256 layout: the
-    // pair q, q + 1 of every thread of the column lies side by side, so a
-    // request of the 16 threads covers 256 contiguous bytes); the amplitudes
-    // and the first half of the carry are requested ahead of the forward
-    // column transform, the second half after it
-    const size_t qb = (size_t)frame * MM + (size_t)quarter * QE;
-    const unsigned cofs = (unsigned)col * M + 2u * j;
-    float2 uc[8];
-    float ac[16];
-#pragma unroll
-    for (int q = 0; q < 16; q += 2) {
-        const float2 t = ldf2t<STREAM>(A.at + qb, cofs + 16 * q);
-        ac[q] = t.x;
-        ac[q + 1] = t.y;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; q += 2) ld2t<STREAM>(A.u + qb, cofs + 16 * q, uc[q], uc[q + 1]);
     colg_line<1>(v, lds, twl + 256, j, at);
     const float gm = A.g * (1.0f / M), b = A.beta, c1 = 1.f - 2.f * A.beta;
     ModOp<FM_RAAR, M> op{nullptr, nullptr, 0.f};
@@ -1755,8 +1761,19 @@ __device__ float colg_item(const FrameArgs& A, int frame, int quarter, float2* l
             st2t<STREAM>(A.u + qb, cofs + 16 * e, un[0], un[1]);
         }
     }
+    {
+        float r = op.resid;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = r;
+    }
     colg_line<-1>(v, lds, twl + 256, j, at);
-    __syncthreads();   // every column is done with the buffer
+    __syncthreads();   // every column is done with the buffer; the wave sums are in red[]
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int i = 0; i < NT / 64; ++i) s += red[i];
+        A.resid[4 * frame + quarter] = s;
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) lds[colg::l3(j + 16 * q, col)] = v[q];
     __syncthreads();
@@ -1771,8 +1788,6 @@ __device__ float colg_item(const FrameArgs& A, int frame, int quarter, float2* l
             st2t<STREAM>(dst, (unsigned)y * M, make_float2(pr.x, pr.y), make_float2(pr.z, pr.w));
         }
     }
-    __syncthreads();
-    return op.resid;
 }
 
 // Item b (of 32 ceil(K / 8)): XCD b mod 8 takes frames [x F, (x + 1) F) in order
@@ -1791,9 +1806,8 @@ __device__ __forceinline__ void colg_run(const FrameArgs& A, int item, float2* l
     const int frame = xcd * fpx + (local >> 2), quarter = local & 3;
     if (frame >= A.K) return;
     __syncthreads();
-    const float r = A.stream ? colg_item<true>(A, frame, quarter, lds, twl) : colg_item<false>(A, frame, quarter, lds, twl);
-    const float s = block_sum(r, red);
-    if (threadIdx.x == 0) A.resid[4 * frame + quarter] = s;
+    if (A.stream) colg_item<true>(A, frame, quarter, lds, twl, red);
+    else colg_item<false>(A, frame, quarter, lds, twl, red);
 }
 
 __global__ void __launch_bounds__(1024) colg_kernel(FrameArgs A) {
