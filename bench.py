@@ -123,6 +123,43 @@ def _rate(frames: int, ms: float, alg_bytes: float) -> dict:
             "alg_frac_of_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
 
 
+def shard_share_form(iters: int = 20, g: int = 3, G: int = 8) -> dict:
+    """One GPU's share of the large-frame workload under the strip sharding
+    (the top-left rows cut into G = 8 equal ranges, GPU g takes the frames
+    starting in range g; here an interior one, g = 3): about an eighth of the
+    frames on a 2048-wide strip plus halo, Poisson data at 1e8 photons per
+    frame, known probe.  The halo exchange itself is not run."""
+    import numpy as np
+    import torch
+
+    from paper_1602_01448_amd import Plan
+    from sharp_data import gen
+
+    dev = torch.device("cuda", 0)
+    s = gen.config_scan(3)
+    sh = gen.shard_share(s, g, G)
+    K = len(sh["positions"])
+    plan = Plan.tuned(sh["nx"], sh["ny"], s.m, sh["positions"], device=dev)
+    w = torch.from_numpy(s.probe.astype(np.complex64)).to(dev)
+    I = plan.simulate(torch.from_numpy(sh["obj"].astype(np.complex64)).to(dev), w)
+    c = s.photons / (I.double().sum().item() / K)
+    gen_ = torch.Generator(device=dev)
+    gen_.manual_seed(16028)
+    plan.set_data(torch.poisson(I * c, generator=gen_).float()).set_probe((w * float(np.sqrt(c))).contiguous())
+    plan.set_object(torch.from_numpy(sh["psi0"].astype(np.complex64)).to(dev)).raar(20, s.beta)
+    t0, t1 = _events()
+    torch.cuda.synchronize(dev)
+    t0.record()
+    plan.raar(iters, s.beta)
+    t1.record()
+    torch.cuda.synchronize(dev)
+    ms = t0.elapsed_time(t1) / iters
+    B = 36 * K * s.m * s.m + 20 * sh["nx"] * sh["ny"]
+    return {"workload": f"one GPU's share of the large-frame scan (strip {g} of {G}): {K} frames 256x256 on a "
+                        f"{sh['ny']}x{sh['nx']} strip + halo", "frames": K, "frame_launch": plan.info()["frame_launch"],
+            "ms_per_iteration": round(ms, 5), **_rate(K, ms, B), "alg_bytes_per_iteration": B}
+
+
 def plain_small_form(iters: int = 200) -> dict:
     """The small plain workload: object 128^2, 169 frames of 32^2 (raster step
     8), noiseless, known probe, beta 0.75.  Launch-latency bound: one
@@ -614,6 +651,7 @@ def main() -> int:
     if not args.no_forms:
         out["forms"] = {}
         for name, fn in (("plain_small", plain_small_form), ("probe_refinement", probe_refinement_form),
+                         ("one_gpu_share", shard_share_form),
                          ("grad", grad_form), ("batched", batched_form), ("batched_small", batched_small_form),
                          ("paper_fig3", fig3_form), ("probe_constraints", probe_form)):
             print(f"bench: form {name}", file=sys.stderr, flush=True)

@@ -241,6 +241,26 @@ def batch_scans(count: int = 32, n_range=(256, 1024), m_choices=(64, 128, 256),
     return scans
 
 
+def shard_share(scan: Scan, g: int, G: int) -> dict:
+    """One GPU's share of `scan` under a split into G horizontal strips: the
+    range of top-left rows [0, n - m] is cut into G equal parts and GPU g takes
+    the frames whose top-left row lies in part g (equal cuts of the object
+    itself would leave the last GPU without frames, since no frame starts
+    below n - m).  Returns those frames with positions relative to the part's
+    first row, the object rows they read (the strip plus a halo of m - 1 rows)
+    as (ny, nx), and the true and start objects cut to them."""
+    n, m = scan.n, scan.m
+    span = n - m + 1
+    y0, y1 = g * span // G, (g + 1) * span // G
+    sel = np.where((scan.positions[:, 0] >= y0) & (scan.positions[:, 0] < y1))[0]
+    pos = scan.positions[sel].copy()
+    pos[:, 0] -= y0
+    ny = min(n - y0, int(pos[:, 0].max()) + m) if len(sel) else 0
+    return {"ny": ny, "nx": n, "m": m, "positions": np.ascontiguousarray(pos, dtype=np.int32), "frames": sel,
+            "obj": scan.obj[y0:y0 + ny].copy(), "psi0": scan.psi0[y0:y0 + ny].copy(), "probe": scan.probe,
+            "row0": y0}
+
+
 def small_batch_scans(count: int = 64) -> list:
     """Many small independent scans for the batched form: each has the shape
     of workload 1 (object 128 x 128, 169 frames of 32 x 32 on a 13 x 13

@@ -54,3 +54,21 @@ def test_batch_scans():
         assert 100 <= s.K <= 1500
         assert s.positions.min() >= 0 and s.positions.max() <= s.n - s.m
     assert len({s.m for s in scans}) == 3
+
+
+def test_shard_share_partitions_the_frames():
+    """The strip shares of the large-frame scan partition its frames; each
+    share's positions fit its strip + halo, and its object rows are the
+    scan's rows from the strip start."""
+    s = gen.config_scan(3)
+    seen = []
+    for g in range(8):
+        sh = gen.shard_share(s, g, 8)
+        pos = sh["positions"]
+        assert 200 <= len(pos) <= 320   # about K / 8 each
+        assert pos[:, 0].min() >= 0 and pos[:, 0].max() < (s.n - s.m + 1 + 7) // 8
+        assert (pos[:, 0] + s.m <= sh["ny"]).all() and (pos[:, 1] + s.m <= sh["nx"]).all()
+        assert np.array_equal(pos[:, 0] + sh["row0"], s.positions[sh["frames"], 0])
+        assert np.array_equal(sh["obj"], s.obj[sh["row0"]:sh["row0"] + sh["ny"]])
+        seen.extend(sh["frames"].tolist())
+    assert sorted(seen) == list(range(s.K))

@@ -4,6 +4,8 @@ determinism, checkpoint/resume and error reporting.
 Acceptance: object after 10 iterations within 1e-4 D-weighted
 (||D (psi_gpu - psi_ref)|| / ||D psi_ref||, D = diag(Q*Q)), eps_a history
 within 1e-4 relative, probe within 1e-4 normwise."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -152,6 +154,39 @@ def test_large_frames_three_iterations_full_object(form):
     del p
     ref = O.raar(I.astype(np.float64), s.positions, (s.n, s.n), s.m, 3, s.beta, psi0=psi0, w0=w)
     D = O.illumination_density(w, s.positions, (s.n, s.n))
+    check_object(got, ref["psi"], D, 1e-4)
+    assert np.max(np.abs(eps - ref["eps_a"]) / ref["eps_a"]) < 1e-4
+
+
+@functools.lru_cache(maxsize=1)
+def _shard_case():
+    """Strip 3 of 8 of the large-frame scan (270 frames of 256^2 on a 466 x 2048
+    strip + halo), Poisson data at 1e8 photons per frame, known probe, and the
+    oracle's three iterations on it (computed once for both forms)."""
+    s = gen.config_scan(3)
+    sh = gen.shard_share(s, 3, 8)
+    pos, ny, nx = sh["positions"], sh["ny"], sh["nx"]
+    I = O.forward_intensity(sh["obj"], s.probe, pos)
+    I, c = gen.apply_poisson(I, s.photons, np.random.default_rng(16029))
+    w, psi0 = c64(np.sqrt(c) * s.probe), c64(sh["psi0"])
+    ref = O.raar(I.astype(np.float64), pos, (ny, nx), s.m, 3, s.beta, psi0=psi0, w0=w)
+    D = O.illumination_density(w, pos, (ny, nx))
+    return s, pos, ny, nx, I, w, psi0, ref, D
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("form", [2, 3])
+def test_one_gpu_share_of_large_frames(form):
+    """One GPU's share under the strip sharding of the large-frame scan
+    (rectangular object, frames of one strip): the whole object and the eps_a
+    history after three iterations against the oracle, both large-frame
+    forms."""
+    from paper_1602_01448_amd import Plan
+    s, pos, ny, nx, I, w, psi0, ref, D = _shard_case()
+    p = Plan(nx, ny, s.m, pos, frame_launch=form)
+    assert p.info()["frame_launch"] == form
+    p.set_data(to_dev(I)).set_probe(to_dev(w)).set_object(to_dev(psi0)).raar(3, s.beta)
+    got, eps = to_host(p.object()), p.metrics()
     check_object(got, ref["psi"], D, 1e-4)
     assert np.max(np.abs(eps - ref["eps_a"]) / ref["eps_a"]) < 1e-4
 
