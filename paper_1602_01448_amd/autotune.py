@@ -111,11 +111,25 @@ def _synthetic(plan: Plan, seed: int):
     return obj.to(torch.complex64).contiguous(), probe.contiguous()
 
 
+def _settle(run, warm_ms: float = 50.0) -> None:
+    """Run `run()` (one step) for about `warm_ms` of GPU time (5 to 200 steps)
+    before anything is timed: the clocks take some tens of milliseconds of
+    steady work to settle."""
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    run()
+    t1.record()
+    torch.cuda.synchronize()
+    n = int(min(200, max(5, warm_ms / max(t0.elapsed_time(t1), 1e-3))))
+    for _ in range(n):
+        run()
+
+
 def _time_raar(plan: Plan, iters: int, reps: int) -> float:
     obj, probe = _synthetic(plan, 1602)
     I = plan.simulate(obj, probe)
     plan.set_data(I).set_probe(probe).set_object(torch.ones_like(obj))
-    plan.raar(1, 0.75)
+    _settle(lambda: plan.raar(1, 0.75))
     best = float("inf")
     for _ in range(reps):
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -130,13 +144,12 @@ def _time_raar(plan: Plan, iters: int, reps: int) -> float:
 
 
 def _time_grad(plan: Plan, reps: int, calls: int = 20) -> float:
-    """Best over `reps` of the mean time of `calls` back-to-back calls (after
-    as many unmeasured ones, so that the clocks have settled)."""
+    """Best over `reps` of the mean time of `calls` back-to-back calls, after
+    the clocks have settled."""
     obj, probe = _synthetic(plan, 1603)
     plan.set_data(plan.simulate(obj, probe))
     psi = torch.ones_like(obj)
-    for _ in range(calls):
-        plan.grad(psi, probe)
+    _settle(lambda: plan.grad(psi, probe))
     best = float("inf")
     for _ in range(reps):
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -225,6 +238,7 @@ def _time_batch(scans, opts, iters: int, reps: int) -> float:
         plans.append(p)
     b = Batch(plans)
     b.raar(iters, 0.75)          # graph capture
+    _settle(lambda: b.raar(iters, 0.75))
     best = float("inf")
     for _ in range(reps):
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
