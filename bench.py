@@ -115,6 +115,20 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
+def _settle(run, warm_ms: float = 50.0) -> None:
+    """Untimed steps (`run()` each) for about `warm_ms` of GPU time, 5 to 500
+    of them, before a form's timed region: the clocks take some tens of
+    milliseconds of steady work to settle."""
+    import torch
+    t0, t1 = _events()
+    t0.record()
+    run()
+    t1.record()
+    torch.cuda.synchronize()
+    for _ in range(int(min(500, max(5, warm_ms / max(t0.elapsed_time(t1), 1e-3))))):
+        run()
+
+
 def _rate(frames: int, ms: float, alg_bytes: float) -> dict:
     """frames/s and algorithmic GB/s (with its fraction of the HBM peak) for
     `frames` frame-iterations moving `alg_bytes` in `ms` milliseconds."""
@@ -147,6 +161,7 @@ def shard_share_form(iters: int = 20, g: int = 3, G: int = 8) -> dict:
     gen_.manual_seed(16028)
     plan.set_data(torch.poisson(I * c, generator=gen_).float()).set_probe((w * float(np.sqrt(c))).contiguous())
     plan.set_object(torch.from_numpy(sh["psi0"].astype(np.complex64)).to(dev)).raar(20, s.beta)
+    _settle(lambda: plan.raar(1, s.beta))
     t0, t1 = _events()
     torch.cuda.synchronize(dev)
     t0.record()
@@ -177,6 +192,7 @@ def plain_small_form(iters: int = 200) -> dict:
     w = torch.from_numpy(s.probe.astype(np.complex64)).to(dev)
     plan.set_data(plan.simulate(obj, w)).set_probe(w)
     plan.set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev)).raar(10, s.beta)
+    _settle(lambda: plan.raar(1, s.beta))
     t0, t1 = _events()
     torch.cuda.synchronize(dev)
     t0.record()
@@ -214,6 +230,7 @@ def probe_refinement_form(iters: int = 50) -> dict:
     g.manual_seed(16022)
     plan.set_data(torch.poisson(I * c, generator=g).float()).init_probe()
     plan.set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev)).raar(5, s.beta)
+    _settle(lambda: plan.raar(1, s.beta))
     t0, t1 = _events()
     torch.cuda.synchronize(dev)
     t0.record()
@@ -251,8 +268,7 @@ def grad_form(reps: int = 10) -> dict:
     plan.set_data(I)
     tpsi = torch.from_numpy(psi.astype(np.complex64)).to(dev)
     tw = torch.from_numpy(w.astype(np.complex64)).to(dev)
-    for _ in range(3):
-        plan.grad(tpsi, tw)
+    _settle(lambda: plan.grad(tpsi, tw))
     torch.cuda.synchronize(dev)
     t0, t1 = _events()
     t0.record()
@@ -292,6 +308,7 @@ def probe_form(iters: int = 20) -> dict:
         if center:
             plan.set_probe_constraint(mask=mask)
         plan.set_object(torch.from_numpy(s.psi0.astype(np.complex64)).to(dev)).raar(2, s.beta)
+        _settle(lambda: plan.raar(1, s.beta))
         t0, t1 = _events()
         torch.cuda.synchronize(dev)
         t0.record()
