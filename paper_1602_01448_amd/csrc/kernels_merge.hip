@@ -250,9 +250,6 @@ __global__ void __launch_bounds__(256) set_data_kernel(const float* __restrict__
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// Fixed-order sum of n partials by one 256-thread block: thread t adds the
-// values t, t + 256, ... in eight interleaved running sums (independent loads
-// in flight), which are then combined in a fixed order.
 // Fixed-order sum of n partials by one workgroup of kRedThreads threads:
 // thread t keeps eight running sums over partials t + k kRedThreads (k mod 8
 // picks the sum), the eight are added pairwise, then the workgroup's values
