@@ -136,9 +136,14 @@ __device__ __forceinline__ void merge_tile(const MergeArgs& A, int tile, int chu
 // that XCD's L2 for the second tile.
 __device__ __forceinline__ int xcd_order(int b, int G) { return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3); }
 
+__device__ void eps_epilogue(const EpsArgs& E);
+
+// Workgroup (0, 0) also forms eps_a when E.partials is set; it reads only
+// the frame launch's partials, which are complete before the merge starts.
 template <int T, int KIND>
-__global__ void __launch_bounds__(256) merge_kernel(MergeArgs A) {
+__global__ void __launch_bounds__(256) merge_kernel(MergeArgs A, EpsArgs E) {
     merge_tile<T, KIND>(A, xcd_order(blockIdx.x, gridDim.x), blockIdx.y);
+    if (E.partials && blockIdx.x == 0 && blockIdx.y == 0) eps_epilogue(E);
 }
 
 // Second merge pass: chunk partials of one tile added in chunk order.
@@ -175,31 +180,32 @@ __global__ void __launch_bounds__(256) merge_finish_kernel(MergeArgs A) {
 }
 
 template <int T, int KIND>
-static hipError_t launch_merge_tk(const MergeArgs& A, int tiles, hipStream_t s) {
-    hipLaunchKernelGGL((merge_kernel<T, KIND>), dim3(tiles, A.split), dim3(256), 0, s, A);
+static hipError_t launch_merge_tk(const MergeArgs& A, int tiles, hipStream_t s, const EpsArgs& E) {
+    hipLaunchKernelGGL((merge_kernel<T, KIND>), dim3(tiles, A.split), dim3(256), 0, s, A, E);
     if (A.split > 1) hipLaunchKernelGGL((merge_finish_kernel<T, KIND>), dim3(tiles), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
 template <int T>
-static hipError_t launch_merge_t(int kind, const MergeArgs& A, int tiles, hipStream_t s) {
+static hipError_t launch_merge_t(int kind, const MergeArgs& A, int tiles, hipStream_t s, const EpsArgs& E) {
     switch (kind) {
-        case MK_V: return launch_merge_tk<T, MK_V>(A, tiles, s);
-        case MK_VU: return launch_merge_tk<T, MK_VU>(A, tiles, s);
-        case MK_U: return launch_merge_tk<T, MK_U>(A, tiles, s);
-        case MK_RAW: return launch_merge_tk<T, MK_RAW>(A, tiles, s);
-        case MK_RAWW: return launch_merge_tk<T, MK_RAWW>(A, tiles, s);
-        case MK_OBJ: return launch_merge_tk<T, MK_OBJ>(A, tiles, s);
-        case MK_DENS: return launch_merge_tk<T, MK_DENS>(A, tiles, s);
+        case MK_V: return launch_merge_tk<T, MK_V>(A, tiles, s, E);
+        case MK_VU: return launch_merge_tk<T, MK_VU>(A, tiles, s, E);
+        case MK_U: return launch_merge_tk<T, MK_U>(A, tiles, s, E);
+        case MK_RAW: return launch_merge_tk<T, MK_RAW>(A, tiles, s, E);
+        case MK_RAWW: return launch_merge_tk<T, MK_RAWW>(A, tiles, s, E);
+        case MK_OBJ: return launch_merge_tk<T, MK_OBJ>(A, tiles, s, E);
+        case MK_DENS: return launch_merge_tk<T, MK_DENS>(A, tiles, s, E);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_merge(int kind, const MergeArgs& A, int tiles, hipStream_t s) {
+hipError_t launch_merge(int kind, const MergeArgs& A, int tiles, hipStream_t s, const EpsArgs* eps) {
+    const EpsArgs E = eps ? *eps : EpsArgs{};
     switch (A.T) {
-        case 16: return launch_merge_t<16>(kind, A, tiles, s);
-        case 32: return launch_merge_t<32>(kind, A, tiles, s);
-        case 64: return launch_merge_t<64>(kind, A, tiles, s);
+        case 16: return launch_merge_t<16>(kind, A, tiles, s, E);
+        case 32: return launch_merge_t<32>(kind, A, tiles, s, E);
+        case 64: return launch_merge_t<64>(kind, A, tiles, s, E);
     }
     return hipErrorInvalidValue;
 }
@@ -299,6 +305,56 @@ __global__ void __launch_bounds__(kRedThreads) eps_kernel(const float* __restric
         const float e = na2 > 0.f ? sqrtf(s / na2) : 0.f;
         hist[idx] = e;
         if (!isfinite(e)) flag[0] = 1;
+    }
+}
+
+// reduce_fixed's sum by a 256-thread workgroup: thread t plays threads
+// t + 256 v (v < 4) of the kRedThreads-thread reduction -- each with its eight
+// running sums and its wavefront's shuffle sums (lane t mod 64 of wave
+// t / 64 + 4 v) -- then thread 0 adds the sixteen wave sums in that order:
+// the same additions, so the same bits.
+__device__ float reduce_fixed256(const float* __restrict__ partials, int n, float* red) {
+    static_assert(kRedThreads == 1024, "four played threads per thread");
+    float sv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int i = threadIdx.x + 256 * v;
+        for (; i + 7 * kRedThreads < n; i += 8 * kRedThreads) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += partials[i + k * kRedThreads];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (i + k * kRedThreads < n) acc[k] += partials[i + k * kRedThreads];
+        float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        sv[v] = s;
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(threadIdx.x >> 6) + 4 * v] = sv[v];
+    }
+    __syncthreads();
+    float t = 0.f;
+    if (threadIdx.x == 0) {
+        float q[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) q[g] = (red[4 * g] + red[4 * g + 1]) + (red[4 * g + 2] + red[4 * g + 3]);
+        t = (q[0] + q[1]) + (q[2] + q[3]);
+    }
+    return t;
+}
+
+__device__ void eps_epilogue(const EpsArgs& E) {
+    __shared__ float red[kRedThreads / 64];
+    const float s = reduce_fixed256(E.partials, E.n, red);
+    if (threadIdx.x == 0) {
+        const float na2 = E.norm_a2[0];
+        const float e = na2 > 0.f ? sqrtf(s / na2) : 0.f;
+        E.hist[E.idx] = e;
+        if (!isfinite(e)) E.flag[0] = 1;
     }
 }
 

@@ -566,10 +566,15 @@ static int one_iteration(sharp_plan_s& p, float beta) {
             HIPCHK(launch_copy(p.ws + p.off.w_gat, p.ws + p.off.w_cur, (size_t)p.m * p.m * sizeof(float2), s));
         p.gat_stale = false;
     }
-    if (t) t->begin(TC_REDUCE);
-    HIPCHK(launch_eps(p.at<float>(p.off.resid), blocks, p.at<float>(p.off.scal), p.at<float>(p.off.hist),
-                      (int)(p.hist_count % kHistCap), p.at<int>(p.off.flag), s));
-    if (t) t->end(TC_REDUCE);
+    // eps_a: formed by a workgroup of the tile merge that follows (same sum,
+    // bit for bit), or by a launch of its own before the strip pass's merge
+    const EpsArgs E{p.at<float>(p.off.resid), blocks, p.at<float>(p.off.scal), p.at<float>(p.off.hist),
+                    (int)(p.hist_count % kHistCap), p.at<int>(p.off.flag)};
+    if (p.strip_form()) {
+        if (t) t->begin(TC_REDUCE);
+        HIPCHK(launch_eps(E.partials, E.n, E.norm_a2, E.hist, E.idx, E.flag, s));
+        if (t) t->end(TC_REDUCE);
+    }
     p.hist_count++;
     p.g = beta;
     MergeArgs Mg = merge_args(p);
@@ -577,7 +582,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     if (p.carry_form()) {
         if (!p.strip_form()) {  // m = 128: the frame kernel wrote v; tile merge
             if (t) t->begin(TC_MERGE);
-            HIPCHK(launch_merge(MK_V, Mg, p.ntiles, s));
+            HIPCHK(launch_merge(MK_V, Mg, p.ntiles, s, &E));
             if (t) t->end(TC_MERGE);
         }
         if (probe_due) {
@@ -592,7 +597,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
         }
     } else {
         if (t) t->begin(TC_MERGE);
-        HIPCHK(launch_merge(probe_due ? MK_VU : MK_V, Mg, p.ntiles, s));
+        HIPCHK(launch_merge(probe_due ? MK_VU : MK_V, Mg, p.ntiles, s, &E));
         if (t) t->end(TC_MERGE);
     }
     if (probe_due) {

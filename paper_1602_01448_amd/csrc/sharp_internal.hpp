@@ -122,7 +122,19 @@ hipError_t launch_grad_probe_partial(int M, int K, const int* pos, int nx, int n
                                      const float2* psi, int chunks, float2* part, hipStream_t s);
 
 // launchers (kernels_merge.hip)
-hipError_t launch_merge(int kind, const MergeArgs& a, int tiles, hipStream_t s);
+// eps_a of an iteration (Eq. (amplitudemetric)) formed by one workgroup of a
+// merge launch instead of a launch of its own: the fixed-order sum of the
+// residual partials (the order of the separate reduction, bit for bit),
+// sqrt(sum / ||a||^2) into hist[idx], flag[0] = 1 when not finite
+struct EpsArgs {
+    const float* __restrict__ partials;   // nullptr: no eps
+    int n;
+    const float* __restrict__ norm_a2;
+    float* __restrict__ hist;
+    int idx;
+    int* __restrict__ flag;
+};
+hipError_t launch_merge(int kind, const MergeArgs& a, int tiles, hipStream_t s, const EpsArgs* eps = nullptr);
 // a2: optional second amplitude copy, 128 x 128 frames transposed (a2_q256 = 0)
 // or 256 x 256 frames in the q256 layout (a2_q256 = 1)
 hipError_t launch_set_data(const float* I, float* a, size_t n, float* partials, int* flag,
