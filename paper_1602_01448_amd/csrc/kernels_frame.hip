@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "fft_lds.hpp"
+#include "reduce_fixed.hpp"
 #include "sharp_internal.hpp"
 
 namespace sharp {
@@ -2076,7 +2077,9 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
     if (S.next_gather) strip_gather_next(A, S, b, e, lds, tw, acc);
 }
 
-__global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripArgs S) {
+// The last workgroup (the lightest strip in the heaviest-first order) also
+// forms eps_a when E.partials is set.
+__global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripArgs S, EpsArgs E) {
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* twl = smem + pidx(16 * 256);
@@ -2087,6 +2090,7 @@ __global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripA
     const int strip = S.order ? S.order[slot] : slot;
     if (S.k1major) strip_merge_item<true>(A, S, strip, lds, twl, acc);
     else strip_merge_item<false>(A, S, strip, lds, twl, acc);
+    if (E.partials && blockIdx.x == gridDim.x - 1) eps_epilogue(E);
 }
 
 // Batched form: phase 0 gather + row FFTs, 1 column pass with the carry,
@@ -2124,14 +2128,22 @@ __global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(co
 
 size_t carry_phase_smem() { return MP<256, 256>::SMEM; }
 
+// Allows `f` all of a CU's 160 KiB of LDS that its static shared arrays leave
+// for dynamic shared memory (the runtime rejects a larger limit).
+static hipError_t allow_full_lds(const void* f) {
+    hipFuncAttributes fa{};
+    hipError_t e = hipFuncGetAttributes(&fa, f);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - fa.sharedSizeBytes));
+}
+
 hipError_t batch_carry_prepare(int phase, size_t smem, int* blocks_per_cu) {
     hipError_t e = hipSuccess;
     int nb = 0;
     if (phase == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_carry_kernel<0>, 256, smem);
     else if (phase == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_carry_kernel<1>, 256, smem);
     else {
-        e = hipFuncSetAttribute((const void*)batch_carry_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                160 * 1024);
+        e = allow_full_lds((const void*)batch_carry_kernel<2>);
         if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_carry_kernel<2>, 256, smem);
     }
     *blocks_per_cu = nb > 0 ? nb : 1;
@@ -2286,20 +2298,20 @@ hipError_t launch_colg_256(const FrameArgs& A, hipStream_t s, const Timer* tp) {
 }
 
 hipError_t launch_strip_256(const FrameArgs& A, const StripArgs& S, int s0, int s1, hipStream_t s,
-                            const Timer* tp) {
+                            const Timer* tp, const EpsArgs* eps) {
     const Timer& t = tp ? *tp : kNoTimer;
     if (s1 <= s0) return hipSuccess;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)strip_merge_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = allow_full_lds((const void*)strip_merge_kernel);
         if (e != hipSuccess) return e;
         attr = true;
     }
     StripArgs S2 = S;
     S2.strip0 = s0;
     t.begin(TC_MERGE, s);
-    hipLaunchKernelGGL(strip_merge_kernel, dim3(s1 - s0), dim3(256), strip_smem_bytes(S.SH, A.nx), s, A, S2);
+    const EpsArgs E = eps ? *eps : EpsArgs{};
+    hipLaunchKernelGGL(strip_merge_kernel, dim3(s1 - s0), dim3(256), strip_smem_bytes(S.SH, A.nx), s, A, S2, E);
     t.end(TC_MERGE, s);
     return hipGetLastError();
 }

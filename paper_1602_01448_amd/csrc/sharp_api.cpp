@@ -530,24 +530,32 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     A.beta = beta;
     int blocks = 0;
     const Timer* t = p.tm();
+    // eps_a of the iteration: formed by a workgroup of the merge launch that
+    // follows the frame phase (the separate reduction's sum, bit for bit)
+    auto eps_args = [&](int n) {
+        return EpsArgs{p.at<float>(p.off.resid), n, p.at<float>(p.off.scal), p.at<float>(p.off.hist),
+                       (int)(p.hist_count % kHistCap), p.at<int>(p.off.flag)};
+    };
     if (p.colg_form()) {
         // column pass with its own gather and row transform, then the strip
         // merge of its k1-major rows; psi_v is final afterwards
         const StripArgs S{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
                           p.at<float2>(p.off.psi_v), p.SH, 0, 0, 1, p.at<int>(p.off.sord)};
-        HIPCHK(launch_colg_256(A, s, t));
-        HIPCHK(launch_strip_256(A, S, 0, p.nstrips, s, t));
         blocks = p.K * 4;
+        const EpsArgs E = eps_args(blocks);
+        HIPCHK(launch_colg_256(A, s, t));
+        HIPCHK(launch_strip_256(A, S, 0, p.nstrips, s, t, &E));
     } else if (p.strip_form()) {
         // frame phase and merge in one sequence; psi_v is final afterwards.  The
         // strip pass also prepares the next iteration's gather unless a probe
         // update (which reuses the stage buffer) follows.
         const StripArgs S{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
                           p.at<float2>(p.off.psi_v), p.SH, probe_due ? 0 : 1, 0, 0, p.at<int>(p.off.sord)};
+        blocks = p.K * 16;
+        const EpsArgs E = eps_args(blocks);
         if (!p.stage_gather) HIPCHK(launch_row_gather_256(A, s, t));
         HIPCHK(launch_col_carry_256(A, s, t));
-        HIPCHK(launch_strip_256(A, S, 0, p.nstrips, s, t));
-        blocks = p.K * 16;
+        HIPCHK(launch_strip_256(A, S, 0, p.nstrips, s, t, &E));
         p.stage_gather = !probe_due;
     } else if (p.carry_form()) {
         HIPCHK(launch_fc128(A, s, t, &blocks));
@@ -566,15 +574,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
             HIPCHK(launch_copy(p.ws + p.off.w_gat, p.ws + p.off.w_cur, (size_t)p.m * p.m * sizeof(float2), s));
         p.gat_stale = false;
     }
-    // eps_a: formed by a workgroup of the tile merge that follows (same sum,
-    // bit for bit), or by a launch of its own before the strip pass's merge
-    const EpsArgs E{p.at<float>(p.off.resid), blocks, p.at<float>(p.off.scal), p.at<float>(p.off.hist),
-                    (int)(p.hist_count % kHistCap), p.at<int>(p.off.flag)};
-    if (p.strip_form()) {
-        if (t) t->begin(TC_REDUCE);
-        HIPCHK(launch_eps(E.partials, E.n, E.norm_a2, E.hist, E.idx, E.flag, s));
-        if (t) t->end(TC_REDUCE);
-    }
+    const EpsArgs E = eps_args(blocks);   // tile-merge forms
     p.hist_count++;
     p.g = beta;
     MergeArgs Mg = merge_args(p);

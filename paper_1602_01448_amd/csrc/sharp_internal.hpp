@@ -140,8 +140,6 @@ hipError_t launch_merge(int kind, const MergeArgs& a, int tiles, hipStream_t s, 
 hipError_t launch_set_data(const float* I, float* a, size_t n, float* partials, int* flag,
                            hipStream_t s, int* blocks_used, int blocked256, float* a2, int a2_q256);
 hipError_t launch_reduce(const float* partials, int n, float* out, hipStream_t s);
-hipError_t launch_eps(const float* partials, int n, const float* norm_a2, float* hist, int idx,
-                      int* flag, hipStream_t s);
 hipError_t launch_loss(const float* partials, int n, float* out, int* flag, hipStream_t s);
 hipError_t launch_mean_amp(const float* a, int K, int M, float2* out, hipStream_t s);
 hipError_t launch_roll_probe(const float2* src, int M, float2* w_cur, float2* w_gat, hipStream_t s);
@@ -211,7 +209,8 @@ size_t strip_smem_bytes(int SH, int nx);
 // column pass over the K frames of A, strip pass over strips [s0, s1)
 hipError_t launch_row_gather_256(const FrameArgs& A, hipStream_t s, const Timer* t);
 hipError_t launch_col_carry_256(const FrameArgs& A, hipStream_t s, const Timer* t);
-hipError_t launch_strip_256(const FrameArgs& A, const StripArgs& S, int s0, int s1, hipStream_t s, const Timer* t);
+hipError_t launch_strip_256(const FrameArgs& A, const StripArgs& S, int s0, int s1, hipStream_t s, const Timer* t,
+                            const EpsArgs* eps = nullptr);
 hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s, int layout = CL_CB256);
 hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s, int layout = CL_CB256);
 // m = 256, form 3: column pass that forms its own gathered row transform
