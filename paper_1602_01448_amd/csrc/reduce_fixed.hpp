@@ -85,8 +85,11 @@ __device__ inline void eps_epilogue(const EpsArgs& E) {
     __shared__ float red[kRedThreads / 64];
     const float s = reduce_fixed256(E.partials, E.n, red);
     if (threadIdx.x == 0) {
-        const float na2 = E.norm_a2[0];
-        const float e = na2 > 0.f ? sqrtf(s / na2) : 0.f;
+        float e = s;   // no norm: the sum itself (the gradient's loss)
+        if (E.norm_a2) {
+            const float na2 = E.norm_a2[0];
+            e = na2 > 0.f ? sqrtf(s / na2) : 0.f;
+        }
         E.hist[E.idx] = e;
         if (!isfinite(e)) E.flag[0] = 1;
     }

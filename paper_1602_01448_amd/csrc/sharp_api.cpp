@@ -703,7 +703,11 @@ extern "C" int sharp_grad(sharp_plan p, const void* d_psi, const void* d_w, floa
     const bool residual_form = p->m == 128 && p->carry_form();
     if (residual_form) HIPCHK(launch_fc128_grad(A, p->grad_groups, s, p->tm(), &blocks));
     else HIPCHK(launch_frame(FM_GRAD, A, p->grad_groups, s, &blocks, p->tm()));
-    HIPCHK(launch_loss(p->at<float>(p->off.resid), p->m == 256 ? p->K * 16 : blocks, d_loss, p->at<int>(p->off.flag), s));
+    // the loss: the fixed-order sum of the frame launch's partials, formed by
+    // a workgroup of the object-gradient merge when there is one (same bits)
+    const EpsArgs L{p->at<float>(p->off.resid), p->m == 256 ? p->K * 16 : blocks, nullptr, d_loss, 0,
+                    p->at<int>(p->off.flag)};
+    if (!d_gpsi) HIPCHK(launch_loss(L.partials, L.n, d_loss, L.flag, s));
     if (d_gpsi) {
         MergeArgs Mg = merge_args(*p);
         Mg.out = (float2*)d_gpsi;
@@ -712,7 +716,7 @@ extern "C" int sharp_grad(sharp_plan p, const void* d_psi, const void* d_w, floa
             Mg.w = (const float2*)d_w;
         }
         if (p->timing) p->timer.begin(TC_MERGE);
-        HIPCHK(launch_merge(residual_form ? MK_RAWW : MK_RAW, Mg, p->ntiles, s));
+        HIPCHK(launch_merge(residual_form ? MK_RAWW : MK_RAW, Mg, p->ntiles, s, &L));
         if (p->timing) p->timer.end(TC_MERGE);
     }
     if (d_gw) {

@@ -125,11 +125,12 @@ hipError_t launch_grad_probe_partial(int M, int K, const int* pos, int nx, int n
 // eps_a of an iteration (Eq. (amplitudemetric)) formed by one workgroup of a
 // merge launch instead of a launch of its own: the fixed-order sum of the
 // residual partials (the order of the separate reduction, bit for bit),
-// sqrt(sum / ||a||^2) into hist[idx], flag[0] = 1 when not finite
+// sqrt(sum / ||a||^2) into hist[idx] -- or, without norm_a2, the sum itself
+// (the gradient's loss) -- and flag[0] = 1 when not finite
 struct EpsArgs {
     const float* __restrict__ partials;   // nullptr: no eps
     int n;
-    const float* __restrict__ norm_a2;
+    const float* __restrict__ norm_a2;    // nullptr: write the sum
     float* __restrict__ hist;
     int idx;
     int* __restrict__ flag;
