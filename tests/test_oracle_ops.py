@@ -307,3 +307,41 @@ def test_P_Q_with_density_threshold_is_the_restricted_projector(rng, n, m, posit
     obj = O.object_update(z, w, pos, (n, n), periodic, eps_D=eps)
     assert np.all(obj.ravel()[~S] == 0)
     assert np.linalg.norm(obj.ravel()[S] - np.linalg.pinv(M) @ z.ravel()) < 1e-12 * np.linalg.norm(obj)
+
+
+def test_extract_is_the_window_and_wraps_periodically(rng):
+    """T_i psi is the m x m window at the frame's top-left corner (Sec.
+    "Forward model"); with periodic boundaries the window wraps modulo the
+    object size: written out index by index."""
+    n, m = 9, 4
+    psi = _crandn(rng, n, n)
+    pos = np.array([(0, 0), (5, 2), (7, 8)], dtype=np.int32)
+    got = O.extract(psi, pos[:2], m)
+    assert np.array_equal(got[0], psi[0:4, 0:4]) and np.array_equal(got[1], psi[5:9, 2:6])
+    got = O.extract(psi, pos, m, periodic=True)
+    for i, (py, px) in enumerate(pos):
+        for ry in range(m):
+            for rx in range(m):
+                assert got[i, ry, rx] == psi[(py + ry) % n, (px + rx) % n]
+
+
+def test_sgn_unit_modulus_and_zero_convention(rng):
+    """sgn(u) = u / |u| with sgn(0) := 1 (Eq. (Pa), reading R2): unit modulus,
+    sgn(u) |u| = u, and exactly 1 at an exact zero (also -0)."""
+    u = _crandn(rng, 50)
+    s = O.sgn(u)
+    assert np.allclose(np.abs(s), 1.0, atol=1e-15) and np.allclose(s * np.abs(u), u, atol=1e-14)
+    z = O.sgn(np.array([0.0 + 0.0j, -0.0 + 0.0j, complex(0.0, -0.0)]))
+    assert np.array_equal(z, np.ones(3, dtype=complex))
+    tiny = O.sgn(np.array([1e-300 + 0j, -1e-300j]))   # nonzero however small: u / |u|, not the zero rule
+    assert np.allclose(tiny, [1.0, -1j], atol=1e-15)
+
+
+@pytest.mark.parametrize("m", [2, 5, 8])
+def test_dft_matrix_entries_and_unitarity(m):
+    """W_jk = e^{+2 pi i jk/m} / sqrt(m), the unitary matrix of the paper's
+    transform (Sec. "Forward model"): its entries written out, and W W* = I."""
+    W = O.dft_matrix(m)
+    j, k = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    assert np.allclose(W, np.exp(2j * np.pi * j * k / m) / np.sqrt(m), atol=1e-15)
+    assert np.allclose(W @ W.conj().T, np.eye(m), atol=1e-14)
