@@ -1566,8 +1566,10 @@ __global__ void __launch_bounds__(256) col_carry_kernel(FrameArgs A) {
 // over n2, and then does what the column pass of the two-pass form does on its
 // 64 columns: column FFTs, Z = U + (g / m) G, eps_a partials, Y = a sgn Z,
 // U' = beta Z + (1 - 2 beta) Y, V = 2Y - Z, inverse column FFTs.  The merge
-// input leaves with each row's 256 values in k1-major order (16 k1 + k2), the
-// order in which the strip pass's line transforms read them.  The four
+// input leaves in octet rows: element (k1, k2) of a row at 128 (k2 / 8) + 8 k1
+// + k2 mod 8, so a quarter writes two runs of 256 bytes per row and a thread
+// of the strip pass's line transforms (one k1, all k2) reads two runs of 64
+// bytes, its 16 neighbours in the line the adjacent runs.  The four
 // workgroups of a frame each repeat the gather and the n1 sums (the price of
 // dropping the row-transformed frame's trip through memory).
 //
@@ -1778,10 +1780,12 @@ __device__ void colg_item(const FrameArgs& A, int frame, int quarter, float2* ld
 #pragma unroll
     for (int q = 0; q < 16; ++q) lds[colg::l3(j + 16 * q, col)] = v[q];
     __syncthreads();
-    // ---- rows of the result: 512 contiguous bytes per row ---------------------
+    // ---- rows of the result in octet rows: 2 x 256 contiguous bytes per row ---
     {
         const int c2 = tid & 31;
-        float2* dst = A.stage + (size_t)frame * MM + 64 * quarter + 2 * c2;
+        // columns c = 2 c2, 2 c2 + 1: k1 = 4 quarter + c / 16, k2 = c mod 16 (even, odd)
+        const int i2 = c2 >> 3, k2 = 2 * (c2 & 7);
+        float2* dst = A.stage + (size_t)frame * MM + 128 * (k2 >> 3) + 8 * (4 * quarter + i2) + (k2 & 7);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int y = (tid >> 5) + 32 * k;
@@ -1969,7 +1973,7 @@ __device__ void strip_gather_next(const FrameArgs& A, const StripArgs& S, int b,
     __syncthreads();
 }
 
-template <bool K1M>
+template <bool OCT>
 __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int strip, float2* lds, const float2* twl,
                                  float2* acc) {
     constexpr int M = 256, NT = 256, LINES = kStripLines, MM = M * M;
@@ -1986,13 +1990,13 @@ __device__ void strip_merge_item(const FrameArgs& A, const StripArgs& S, int str
     float2 v[16];
     // an absent line (record frame -1, row 0, x 0) reads frame 0 row 0: in
     // bounds, and its transform is never summed
-    // element j + 16 r of a line: natural order (stride 16), or k1-major rows
-    // (16 consecutive values)
+    // element j + 16 r of a line (k1 = j, k2 = r): natural order (stride 16),
+    // or octet rows (two runs of eight at 128 (r / 8) + 8 j)
     auto load_line = [&](const int4& rec) {
-        if constexpr (K1M) {
-            const float2* src = A.stage + (size_t)(rec.x < 0 ? 0 : rec.x) * MM + (size_t)rec.y * M + 16 * j;
+        if constexpr (OCT) {
+            const float2* src = A.stage + (size_t)(rec.x < 0 ? 0 : rec.x) * MM + (size_t)rec.y * M + 8 * j;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = src[r];
+            for (int r = 0; r < 16; ++r) v[r] = src[128 * (r >> 3) + (r & 7)];
         } else {
             const float2* src = A.stage + (size_t)(rec.x < 0 ? 0 : rec.x) * MM + (size_t)rec.y * M + j;
 #pragma unroll
@@ -2088,7 +2092,7 @@ __global__ void __launch_bounds__(256, 3) strip_merge_kernel(FrameArgs A, StripA
     __syncthreads();
     const int slot = S.strip0 + blockIdx.x;
     const int strip = S.order ? S.order[slot] : slot;
-    if (S.k1major) strip_merge_item<true>(A, S, strip, lds, twl, acc);
+    if (S.octet_rows) strip_merge_item<true>(A, S, strip, lds, twl, acc);
     else strip_merge_item<false>(A, S, strip, lds, twl, acc);
     if (E.partials && blockIdx.x == gridDim.x - 1) eps_epilogue(E);
 }
@@ -2121,7 +2125,7 @@ __global__ void __launch_bounds__(256, PHASE == 2 ? 3 : 1) batch_carry_kernel(co
         if (threadIdx.x == 0) A.resid[w.y] = s;
     } else {
         const StripArgs& S = CH.s[w.x - CH.base];
-        if (S.k1major) strip_merge_item<true>(A, S, w.y, lds, twl, twl + 256);
+        if (S.octet_rows) strip_merge_item<true>(A, S, w.y, lds, twl, twl + 256);
         else strip_merge_item<false>(A, S, w.y, lds, twl, twl + 256);
     }
 }

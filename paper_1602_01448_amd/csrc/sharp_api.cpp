@@ -538,7 +538,7 @@ static int one_iteration(sharp_plan_s& p, float beta) {
     };
     if (p.colg_form()) {
         // column pass with its own gather and row transform, then the strip
-        // merge of its k1-major rows; psi_v is final afterwards
+        // merge of its octet rows; psi_v is final afterwards
         const StripArgs S{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
                           p.at<float2>(p.off.psi_v), p.SH, 0, 0, 1, p.at<int>(p.off.sord)};
         blocks = p.K * 4;

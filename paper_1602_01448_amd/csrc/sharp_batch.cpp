@@ -221,7 +221,7 @@ extern "C" int sharp_batch_set_workspace(sharp_batch b, void* d, size_t bytes) {
         sharp_plan_s& p = *b->plans[s];
         fa[s] = frame_args(p);
         ma[s] = merge_args(p);
-        // form 3: the column pass gathers for itself and leaves k1-major rows
+        // form 3: the column pass gathers for itself and leaves octet rows
         sa[s] = StripArgs{p.at<int>(p.off.sptr), p.at<int4>(p.off.sln), p.at<float>(p.off.Dinv),
                           p.at<float2>(p.off.psi_v), p.SH, p.colg_form() ? 0 : 1, 0, p.colg_form() ? 1 : 0, nullptr};
         ea[s] = EpsDesc{p.at<float>(p.off.resid), resid_blocks_default(p), 0, p.at<float>(p.off.scal),

@@ -162,7 +162,8 @@ struct StripArgs {
     int next_gather;                 // also form the next iteration's gathered, row-transformed
                                      // frame rows (w * T psi_v) in the stage buffer
     int strip0;                      // first launch slot (workgroup b takes slot strip0 + b)
-    int k1major;                     // stage rows hold element k1 + 16 k2 at 16 k1 + k2 (else natural order)
+    int octet_rows;                  // stage rows hold element k1 + 16 k2 at 128 (k2 / 8) + 8 k1 + k2 mod 8
+                                     // (else natural order)
     const int* __restrict__ order;   // [nstrips] strip of each launch slot, the strips with the most frame
                                      // rows first (nullptr: slot = strip)
 };
@@ -216,7 +217,7 @@ hipError_t launch_carry_to_space(const FrameArgs& A, hipStream_t s, int layout =
 hipError_t launch_space_to_carry(const FrameArgs& A, hipStream_t s, int layout = CL_CB256);
 // m = 256, form 3: column pass that forms its own gathered row transform
 // (quarter-frame workgroups, carry and amplitudes in the q256 layout), writing
-// the merge input with k1-major rows to the stage buffer; one residual partial
+// the merge input in octet rows to the stage buffer; one residual partial
 // per (frame, quarter), at 4 frame + quarter
 hipError_t launch_colg_256(const FrameArgs& A, hipStream_t s, const Timer* t);
 int colg_items(int K);   // workgroups (items) of one launch over K frames
