@@ -73,7 +73,7 @@ typedef struct sharp_options {
     int grad_groups;  /* workgroups of the gradient frame kernel (0 = tuned) */
     int frame_launch; /* m = 128: 0 or 2 = carry kept in the Fourier domain (default),
                          1 = carry in frame space (3 is taken as 2).  m = 256 RAAR:
-                         0 = default (3 when K >= 768, else 2; 1 when the object is
+                         0 = default (3 when K >= 400, else 2; 1 when the object is
                          wider than 8192); 1 = row, column and row passes with the carry
                          in frame space, then the tile merge; 2 = carry kept in the
                          Fourier domain, a column pass reading the row-transformed

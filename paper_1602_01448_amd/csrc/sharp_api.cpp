@@ -175,10 +175,11 @@ static void choose_tuning(sharp_plan_s& p) {
     p.SH = p.m != 256 || p.nx > 8192 ? 0 : (p.opt.strip_rows == 2 && 2 * p.nx <= 8192) ? 2 : 1;
     // m = 256 default: the column pass with its own row transform once the
     // frames are many enough for its 4 K quarter-frame workgroups to fill the
-    // GPU for many rounds (tuned: form 2 faster at 173-474 frames, form 3 at
-    // 899-2025), else the column pass reading the prepared gather
+    // GPU for several rounds (measured on parts of the 2025-frame scan: form 2
+    // 5 % faster at 270 frames, form 3 5 % faster at 495 and 15 % at 990),
+    // else the column pass reading the prepared gather
     p.frame_launch = p.opt.frame_launch ? p.opt.frame_launch
-                                        : (p.m == 256 && p.K >= 768) ? 3 : (p.m >= 128 ? 2 : 1);
+                                        : (p.m == 256 && p.K >= 400) ? 3 : (p.m >= 128 ? 2 : 1);
     if (p.m == 256 && p.frame_launch >= 2 && !p.SH) p.frame_launch = 1;
     if (p.m < 128) p.frame_launch = 1;
     if (p.m == 128 && p.frame_launch == 3) p.frame_launch = 2;

@@ -96,7 +96,7 @@ def test_large_frame_form_selection(L, n, kw, form, rows):
     """m = 256: Fourier-carry form with 1-row strips by default, 2-row strips
     on request while a 2-row strip fits in LDS, frame-space form beyond 8192;
     the form whose column pass forms its own row transform on request, and
-    by default from 768 frames on (n < 0: 800 frames)."""
+    by default from 400 frames on (n < 0: 800 frames)."""
     from paper_1602_01448_amd._lib import SharpPlanInfo
     K = 800 if n < 0 else 2
     n = abs(n)
