@@ -270,10 +270,15 @@ __device__ __forceinline__ float block_sum(float x, float* red) {
 // ---------------------------------------------------------------------------
 // m <= 128: whole frames in LDS
 // ---------------------------------------------------------------------------
+// A workgroup of NT threads holds G frames, E elements per thread.  32^2
+// frames take one frame per 128-thread workgroup (eight elements per thread):
+// half the dependent work per thread of sixteen-element groups, and four
+// times the workgroups (at 169 frames, 169 instead of 43).  The 64^2 radix-16
+// first stage has 256 butterflies per frame, so 64^2 groups keep 256 threads.
 template <int M>
 struct FG {
-    static constexpr int NT = (M == 128) ? 1024 : 256;
-    static constexpr int E = 16;
+    static constexpr int NT = (M == 128) ? 1024 : (M == 32) ? 128 : 256;
+    static constexpr int E = (M == 32) ? 8 : 16;
     static constexpr int G = NT * E / (M * M);
     static constexpr int FE = G * M * M;
     static constexpr int NP = E / 2;
@@ -1130,6 +1135,16 @@ hipError_t launch_frame(int mode, const FrameArgs& A, int grid_hint, hipStream_t
         case 256: return dispatch_m<256>(mode, A, grid_hint, s, blocks_used, t);
     }
     return hipErrorInvalidValue;
+}
+
+int fg_groups(int M) {
+    switch (M) {
+        case 16: return FG<16>::G;
+        case 32: return FG<32>::G;
+        case 64: return FG<64>::G;
+        case 128: return FG<128>::G;
+    }
+    return 1;
 }
 
 int frame_partial_slots(int M, int mode, int blocks) {

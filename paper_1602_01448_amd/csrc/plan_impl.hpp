@@ -17,9 +17,6 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 inline bool supported_m(int m) { return m == 16 || m == 32 || m == 64 || m == 128 || m == 256; }
 
-// frames per frame-kernel group (must match kernels_frame.hip)
-inline int fg_groups(int m) { return m == 16 ? 16 : m == 32 ? 4 : 1; }
-
 struct Offsets {
     size_t tw, pos, tile_ptr, tile_frames, a, a_t, u, v, stage, psi_v, psi_l, tmp_obj, D, Dinv;
     size_t w_cur, w_gat, tmp_w, tmp_w2, pcons, mpart, pnum, pden, gwpart, resid, hist, scal, flag, sptr, sln, sord, total;
