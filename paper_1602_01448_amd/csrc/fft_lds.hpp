@@ -133,7 +133,7 @@ __device__ __forceinline__ void dft(float2* a) {
 template <int N> struct Radix;
 template <> struct Radix<16>  { static constexpr int S = 1, R0 = 16, R1 = 1; };
 template <> struct Radix<32>  { static constexpr int S = 2, R0 = 8,  R1 = 4; };
-template <> struct Radix<64>  { static constexpr int S = 2, R0 = 16, R1 = 4; };
+template <> struct Radix<64>  { static constexpr int S = 2, R0 = 8,  R1 = 8; };
 template <> struct Radix<128> { static constexpr int S = 2, R0 = 16, R1 = 8; };
 template <> struct Radix<256> { static constexpr int S = 2, R0 = 16, R1 = 16; };
 

@@ -270,15 +270,15 @@ __device__ __forceinline__ float block_sum(float x, float* red) {
 // ---------------------------------------------------------------------------
 // m <= 128: whole frames in LDS
 // ---------------------------------------------------------------------------
-// A workgroup of NT threads holds G frames, E elements per thread.  32^2
-// frames take one frame per 128-thread workgroup (eight elements per thread):
-// half the dependent work per thread of sixteen-element groups, and four
-// times the workgroups (at 169 frames, 169 instead of 43).  The 64^2 radix-16
-// first stage has 256 butterflies per frame, so 64^2 groups keep 256 threads.
+// A workgroup of NT threads holds G frames, E elements per thread.  32^2 and
+// 64^2 frames take one frame per workgroup of 128 and 512 threads (eight
+// elements per thread): half the dependent work per thread of sixteen-element
+// groups, and more workgroups (at 169 frames of 32^2, 169 instead of 43).  The
+// 64^2 transforms are radix 8 x 8 (512 butterflies per stage and frame).
 template <int M>
 struct FG {
-    static constexpr int NT = (M == 128) ? 1024 : (M == 32) ? 128 : 256;
-    static constexpr int E = (M == 32) ? 8 : 16;
+    static constexpr int NT = (M == 128) ? 1024 : (M == 32) ? 128 : (M == 64) ? 512 : 256;
+    static constexpr int E = (M == 32 || M == 64) ? 8 : 16;
     static constexpr int G = NT * E / (M * M);
     static constexpr int FE = G * M * M;
     static constexpr int NP = E / 2;
