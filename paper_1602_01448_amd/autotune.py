@@ -192,19 +192,21 @@ def tune_raar(nx: int, ny: int, m: int, positions, periodic: bool = False, iters
 
 def tune_grad(nx: int, ny: int, m: int, positions, periodic: bool = False, reps: int = 5, path: str = CACHE,
               verbose: bool = False) -> dict:
-    """Fastest gradient grid (and merge tile) on this geometry; cached."""
+    """Fastest gradient grid, merge tile and merge frame-chunk split on this
+    geometry; cached."""
     key = geometry_key("grad", nx, ny, m, positions, periodic)
     best, best_t = {}, float("inf")
     for gg in (64, 128, 256, 512, 1024):
         for tile in (16, 32, 64):
-            opts = {"grad_groups": gg, "tile": tile}
-            p = Plan(nx, ny, m, positions, periodic=periodic, **opts)
-            t = _time_grad(p, reps)
-            if verbose:
-                print(f"  {opts}: {t:.4f} ms/call", flush=True)
-            if t < best_t:
-                best, best_t = opts, t
-            del p
+            for split in (1, 2, 4, 8):
+                opts = {"grad_groups": gg, "tile": tile, "merge_split": split}
+                p = Plan(nx, ny, m, positions, periodic=periodic, **opts)
+                t = _time_grad(p, reps)
+                if verbose:
+                    print(f"  {opts}: {t:.4f} ms/call", flush=True)
+                if t < best_t:
+                    best, best_t = opts, t
+                del p
     cache = load_cache(path)
     cache[key] = {"options": best, "ms_per_call": round(best_t, 5), "when": time.strftime("%Y-%m-%d %H:%M:%S")}
     save_cache(cache, path)

@@ -11,20 +11,22 @@ from sharp_data import gen
 pytestmark = pytest.mark.gpu
 
 
-def _setup(cfg):
+def _setup(cfg, **opts):
     from paper_1602_01448_amd import Plan
     s = gen.config_scan(cfg)
     I = O.forward_intensity(s.obj, s.probe, s.positions).astype(np.float32)
     psi, w = gen.gradient_point(s)
     psi, w = c64(psi), c64(w)
-    p = Plan(s.n, s.n, s.m, s.positions)
+    p = Plan(s.n, s.n, s.m, s.positions, **opts)
     p.set_data(to_dev(I))
     return s, p, np.sqrt(I.astype(np.float64)), psi, w
 
 
-@pytest.mark.parametrize("cfg", ["4s", 4])
-def test_gradient_matches_oracle(cfg):
-    s, p, a, psi, w = _setup(cfg)
+# the last case is the benchmark's tuned launch: 16^2 merge tiles whose frame
+# lists are split into four chunks, summed by the second merge pass
+@pytest.mark.parametrize("cfg,opts", [("4s", {}), (4, {}), (4, {"grad_groups": 256, "tile": 16, "merge_split": 4})])
+def test_gradient_matches_oracle(cfg, opts):
+    s, p, a, psi, w = _setup(cfg, **opts)
     loss, gpsi, gw = p.grad(to_dev(psi), to_dev(w))
     L, rpsi, rw = O.amplitude_grad(psi, w, s.positions, a)
     assert abs(loss.item() - L) / L < 1e-5
