@@ -420,14 +420,27 @@ def measured_traffic(kernel: str):
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5) -> dict:
     """Plain device-memory references of known size, timed with HIP events
     (best of `reps`): a copy (nbytes read, nbytes written), a fill (nbytes
-    written) and a sum (nbytes read), all torch's own kernels.  The copy is
-    also what the rocprofv3 memory counters are scaled by: run under
-    rocprofv3 --pmc, its FETCH_SIZE and WRITE_SIZE should read nbytes each."""
+    written) and a sum (nbytes read), torch's own kernels, and a plain read
+    (nbytes read with 16-byte nontemporal loads, the library's
+    sharp_read_reference).  The copy is also what the rocprofv3 memory
+    counters are scaled by: run under rocprofv3 --pmc, its FETCH_SIZE and
+    WRITE_SIZE should read nbytes each."""
+    import ctypes
+
     import torch
+
+    from paper_1602_01448_amd._lib import check, lib
 
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     a.fill_(1.0)
     b = torch.empty_like(a)
+    sink = torch.empty(2048, dtype=torch.float32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def read():
+        check(lib.sharp_read_reference(ctypes.c_void_p(a.data_ptr()), nbytes, ctypes.c_void_p(sink.data_ptr()),
+                                       stream), "sharp_read_reference")
+
     torch.cuda.synchronize()
 
     def best(fn):
@@ -443,11 +456,11 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 5) -> dict:
 
     out = {"bytes": nbytes}
     for name, fn, moved in (("copy", lambda: b.copy_(a), 2 * nbytes), ("fill", lambda: b.fill_(2.0), nbytes),
-                            ("sum", lambda: a.sum(), nbytes)):
+                            ("sum", lambda: a.sum(), nbytes), ("read", read, nbytes)):
         ms = best(fn)
         out[f"{name}_ms"] = round(ms, 4)
         out[f"{name}_GBps"] = round(moved / (ms / 1e3) / 1e9, 1)
-    del a, b
+    del a, b, sink
     torch.cuda.empty_cache()
     print(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
     return out

@@ -294,6 +294,20 @@ int sharp_batch_set_workspace(sharp_batch batch, void* d_workspace, size_t bytes
 int sharp_batch_set_stream(sharp_batch batch, void* stream);
 int sharp_batch_raar_iterate(sharp_batch batch, int n, float beta);
 
+/* ------------------------------------------------------------------------
+ * Device read-rate reference (a measurement utility, not part of the method;
+ * for benchmarks that compare the passes above with what the GPU's memory
+ * delivers): reads `bytes` bytes from d_src with 16-byte nontemporal loads,
+ * eight requests in flight per thread, SHARP_READ_REFERENCE_SINK workgroups
+ * of 256 threads striding over the buffer, and writes one float per
+ * workgroup to d_sink (SHARP_READ_REFERENCE_SINK floats, device memory; the
+ * values carry no meaning).  Asynchronous on `stream` (a hipStream_t; NULL =
+ * null stream).  d_src must be 16-byte aligned and bytes a positive multiple
+ * of 16, else SHARP_ERR_INVALID_ARG; a failed launch gives SHARP_ERR_HIP.
+ * ---------------------------------------------------------------------- */
+#define SHARP_READ_REFERENCE_SINK 2048
+int sharp_read_reference(const void* d_src, size_t bytes, float* d_sink, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

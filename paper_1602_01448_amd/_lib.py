@@ -85,6 +85,7 @@ SIGNATURES = [
     ("sharp_batch_set_workspace", c_int, [c_void_p, c_void_p, c_size_t]),
     ("sharp_batch_set_stream", c_int, [c_void_p, c_void_p]),
     ("sharp_batch_raar_iterate", c_int, [c_void_p, c_int, c_float]),
+    ("sharp_read_reference", c_int, [c_void_p, c_size_t, c_void_p, c_void_p]),
 ]
 
 _lib = None

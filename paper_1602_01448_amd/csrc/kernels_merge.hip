@@ -427,4 +427,32 @@ hipError_t launch_batch_begin(FrameArgs* D, EpsDesc* E, const BatchBegin& b, flo
     return hipGetLastError();
 }
 
+// Device read-rate reference: 16-byte nontemporal loads, eight requests in
+// flight per thread, kReadRefBlocks workgroups striding over the buffer.  The
+// sums only keep the loads alive; thread 0 of each workgroup stores its own.
+__global__ void __launch_bounds__(256) read_reference_kernel(const float4* __restrict__ p, size_t n,
+                                                             float* __restrict__ sink) {
+    typedef float sf4 __attribute__((ext_vector_type(4)));
+    constexpr int U = 8;
+    float acc = 0.f;
+    const size_t stride = (size_t)gridDim.x * 256 * U;
+    for (size_t i = (size_t)blockIdx.x * 256 * U + threadIdx.x; i < n; i += stride) {
+        sf4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t j = i + (size_t)u * 256;
+            v[u] = j < n ? __builtin_nontemporal_load(reinterpret_cast<const sf4*>(p + j)) : sf4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    }
+    if (threadIdx.x == 0) sink[blockIdx.x] = acc;
+}
+
+hipError_t launch_read_reference(const void* src, size_t bytes, float* sink, hipStream_t s) {
+    hipLaunchKernelGGL(read_reference_kernel, dim3(kReadRefBlocks), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(src), bytes / 16, sink);
+    return hipGetLastError();
+}
+
 }  // namespace sharp

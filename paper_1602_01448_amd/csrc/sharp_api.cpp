@@ -40,6 +40,16 @@ static void timer_mark(void* ctx, int cat, int begin, hipStream_t s) {
     }
 }
 
+static_assert(sharp::kReadRefBlocks == SHARP_READ_REFERENCE_SINK, "read-reference sink size");
+
+extern "C" int sharp_read_reference(const void* d_src, size_t bytes, float* d_sink, void* stream) {
+    if (!d_src || !d_sink || bytes == 0 || bytes % 16 || reinterpret_cast<uintptr_t>(d_src) % 16)
+        return SHARP_ERR_INVALID_ARG;
+    return sharp::launch_read_reference(d_src, bytes, d_sink, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? SHARP_OK
+               : SHARP_ERR_HIP;
+}
+
 extern "C" const char* sharp_status_string(int s) {
     switch (s) {
         case SHARP_OK: return "ok";

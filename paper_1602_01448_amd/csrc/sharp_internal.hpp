@@ -111,6 +111,9 @@ hipError_t launch_frame(int mode, const FrameArgs& a, int grid_hint, hipStream_t
                         const Timer* t = nullptr);
 int frame_partial_slots(int M, int mode, int blocks);  // gw partial slots per launch
 int fg_groups(int M);                                   // frames per frame-kernel workgroup, m <= 128
+// device read-rate reference (kernels_merge.hip); sink holds kReadRefBlocks floats
+constexpr int kReadRefBlocks = 2048;
+hipError_t launch_read_reference(const void* src, size_t bytes, float* sink, hipStream_t s);
 hipError_t launch_probe_partial(int M, int K, const int* pos, int nx, int ny, int periodic,
                                 const float2* u, const float2* w, const float2* psi_v,
                                 const float2* psi_l, float beta, int chunks, float2* num, float* den,

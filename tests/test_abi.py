@@ -50,6 +50,16 @@ def _create(L, n, m, pos, **kw):
     return st, h
 
 
+def test_read_reference_rejects_bad_arguments(L):
+    # every case returns before any device work
+    vp = ctypes.c_void_p
+    assert L.sharp_read_reference(None, 16, vp(256), None) == -1
+    assert L.sharp_read_reference(vp(256), 16, None, None) == -1
+    assert L.sharp_read_reference(vp(256), 0, vp(256), None) == -1
+    assert L.sharp_read_reference(vp(256), 24, vp(256), None) == -1
+    assert L.sharp_read_reference(vp(264), 32, vp(256), None) == -1
+
+
 def test_status_strings(L):
     for s in range(-9, 1):
         assert len(L.sharp_status_string(s)) > 0 and L.sharp_status_string(s) != b"unknown status"

@@ -117,3 +117,22 @@ def test_initial_probe(m, K, n):
     p.init_probe()
     got = to_host(p.probe())
     check_close(got, O.init_probe(I.astype(np.float64)), 1e-5)
+
+
+def test_read_reference_runs():
+    """The device read-rate reference (a measurement utility) reads a buffer
+    with a ragged tail and leaves one finite float per workgroup."""
+    import ctypes
+
+    import torch
+
+    from paper_1602_01448_amd._lib import check, lib
+    n = (1 << 20) + 3 * 4   # floats: 4 MiB + 48 bytes, a multiple of 16 bytes
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    sink = torch.full((2048,), float("nan"), dtype=torch.float32, device="cuda")
+    check(lib.sharp_read_reference(ctypes.c_void_p(x.data_ptr()), n * 4, ctypes.c_void_p(sink.data_ptr()), None),
+          "sharp_read_reference")
+    torch.cuda.synchronize()
+    s = sink.cpu()
+    assert torch.isfinite(s).all()
+    assert float(s.sum()) > 0
