@@ -21,12 +21,17 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-command-line-argument",
 ]
+# per-source flags: the frame kernels take the scheduler strategy that groups
+# memory requests into clauses (large-frame column pass 1.5-2.6 % faster, the
+# 128^2 gradient frame kernel 0.8 % slower; the generated arithmetic is the
+# same, results are bit for bit unchanged)
+SOURCE_FLAGS = {"kernels_frame.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
 
 
 def _compile(src: str, extra: list[str]) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
