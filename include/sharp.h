@@ -68,9 +68,14 @@ typedef struct sharp_options {
     int probe_start;  /* first iteration (1-based, counted over the plan's life) with a
                          probe update; 0 means 1 */
     float eps_D;      /* (Q*Q)^{-1} is 1/D where D > eps_D and 0 elsewhere (default 0) */
-    int tile;         /* merge tile side in object pixels: 16, 32 or 64 (0 = tuned) */
-    int merge_split;  /* frame chunks per tile in the first merge pass, >= 1 (0 = tuned) */
-    int grad_groups;  /* workgroups of the gradient frame kernel (0 = tuned) */
+    int tile;         /* merge tile side in object pixels: 16, 32 or 64 (0 = the library's
+                         choice: 32 while that gives >= 1024 tiles, else 16) */
+    int merge_split;  /* frame chunks per tile in the first pass of the tile merges (RAAR,
+                         object output, density, gradient), >= 1 (0 = the library's choice:
+                         >= 1024 workgroups, >= 4 frames per chunk) */
+    int grad_groups;  /* workgroups of the gradient frame kernel (0 = the library's choice).
+                         The Python binding's Plan.tuned fills these from the autotuner's
+                         cache for the geometry. */
     int frame_launch; /* m = 128: 0 or 2 = carry kept in the Fourier domain (default),
                          1 = carry in frame space (3 is taken as 2).  m = 256 RAAR:
                          0 = default (3 when K >= 400, else 2; 1 when the object is
