@@ -48,7 +48,7 @@ def test_gradient_independent_of_partial_count(groups):
     check_close(to_host(gpsi), rpsi, 1e-5)
 
 
-@pytest.mark.parametrize("m,K,n", [(32, 9, 80), (256, 3, 300)])
+@pytest.mark.parametrize("m,K,n", [(32, 9, 80), (64, 12, 160), (256, 3, 300)])
 def test_gradient_other_sizes(m, K, n):
     from paper_1602_01448_amd import Plan
     rng = np.random.default_rng(m)
